@@ -1,0 +1,157 @@
+"""Seeded synthetic workloads shared by the tests, the smoke check and the benchmark.
+
+This module holds problem descriptions and seeded random inputs only: no
+lattice Boltzmann arithmetic. Both the FP64 oracle and the GPU library take
+the same plain-dict problem and the same host arrays from here.
+
+Problem dict keys: ``nx, ny, nu, alpha, g_beta, T0, Fx, Fy, Q`` and ``sides``
+(four dicts, order x-, x+, y-, y+: ``kind`` "periodic"/"wall", ``u_wall``,
+Robin data ``b1, b2, b3`` of ``b1 dT/dn + b2 T = b3`` with n the outward
+normal). Optional rate overrides ``s_b, s_4, s_3, lambda_0, lambda_2``.
+
+The natural-convection parameters follow the problem statement of Sec. 3.3 of
+Fei & Luo (arXiv:1801.04577): Ra = g beta dT H^3/(nu alpha), Pr = nu/alpha and
+a characteristic velocity U = sqrt(g beta dT H), so nu = U H sqrt(Pr/Ra),
+alpha = nu/Pr and g beta = U^2/(H dT).
+"""
+import math
+
+import numpy as np
+
+PERIODIC = {"kind": "periodic"}
+
+
+def dirichlet(T, u_wall=0.0):
+    """Wall held at temperature T: b1 = 0, b2 = 1, b3 = T."""
+    return {"kind": "wall", "b1": 0.0, "b2": 1.0, "b3": float(T), "u_wall": float(u_wall)}
+
+
+def adiabatic(u_wall=0.0):
+    """Insulated wall: b1 = 1, b2 = 0, b3 = 0."""
+    return {"kind": "wall", "b1": 1.0, "b2": 0.0, "b3": 0.0, "u_wall": float(u_wall)}
+
+
+def robin(b1, b2, b3, u_wall=0.0):
+    return {"kind": "wall", "b1": float(b1), "b2": float(b2), "b3": float(b3),
+            "u_wall": float(u_wall)}
+
+
+def problem(nx, ny, nu, alpha, sides, g_beta=0.0, T0=0.0, Fx=0.0, Fy=0.0, Q=0.0, **rates):
+    p = {"nx": int(nx), "ny": int(ny), "nu": float(nu), "alpha": float(alpha),
+         "g_beta": float(g_beta), "T0": float(T0), "Fx": float(Fx), "Fy": float(Fy),
+         "Q": float(Q), "sides": [dict(s) for s in sides]}
+    for k, v in rates.items():
+        assert k in ("s_b", "s_4", "s_3", "lambda_0", "lambda_2"), k
+        p[k] = v
+    return p
+
+
+# --------------------------------------------------------------------------
+# Counter-based noise: splitmix64 of (seed, node index)
+# --------------------------------------------------------------------------
+
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def splitmix64(x):
+    """SplitMix64 output function (Steele, Lea, Flood 2014) on uint64 arrays."""
+    x = np.asarray(x, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = x + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform01(seed, n):
+    """n uniforms in [0, 1) from splitmix64(seed * 2^32 + k), k = 0..n-1."""
+    with np.errstate(over="ignore"):
+        ctr = (np.uint64(seed) << np.uint64(32)) + np.arange(n, dtype=np.uint64)
+    z = splitmix64(ctr)
+    return (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+def noise_field(seed, nx, ny, amplitude):
+    """amplitude * U(-1, 1) per node, [ny][nx] row-major, node index y*nx + x."""
+    u = uniform01(seed, nx * ny).reshape(ny, nx)
+    return amplitude * (2.0 * u - 1.0)
+
+
+# --------------------------------------------------------------------------
+# Named problems
+# --------------------------------------------------------------------------
+
+def channel(nx=64, ny=32, nu=0.05, Pr=0.71, gx=1e-6, Q=1e-4, Tw=0.0):
+    """Body-force channel: periodic in x, no-slip walls in y at temperature Tw,
+    uniform heat source Q, no buoyancy. 64x32 at nu = 0.05, gx = 1e-6, Q = 1e-4 is the
+    small FP32-vs-FP64 parity workload."""
+    return problem(nx, ny, nu, nu / Pr, [PERIODIC, PERIODIC, dirichlet(Tw), dirichlet(Tw)],
+                   Fx=gx, Q=Q)
+
+
+def cavity_params(H, Ra, Pr, U=0.1, dT=1.0):
+    nu = U * H * math.sqrt(Pr / Ra)
+    return nu, nu / Pr, U * U / (H * dT)
+
+
+def cavity(nx, ny=None, Ra=1e5, Pr=0.71, Q=0.0, Th=0.5, Tc=-0.5, U=0.1):
+    """Differentially heated cavity (Sec. 3.3): hot wall at x-, cold wall at x+,
+    adiabatic bottom and top, gravity along -y, H = ny."""
+    ny = nx if ny is None else ny
+    nu, alpha, gb = cavity_params(ny, Ra, Pr, U, Th - Tc)
+    return problem(nx, ny, nu, alpha, [dirichlet(Th), dirichlet(Tc), adiabatic(), adiabatic()],
+                   g_beta=gb, T0=0.5 * (Th + Tc), Q=Q)
+
+
+def cavity_initial_T(prob, seed=12345, amplitude=1e-4):
+    return prob["T0"] + noise_field(seed, prob["nx"], prob["ny"], amplitude)
+
+
+def couette(nx=4, ny=16, nu=0.1, alpha=0.1, U=0.01, Tc=0.0, Th=1.0, Q=0.0):
+    """Bottom wall at rest (Tc), top wall moving with U along x (Th); periodic in x."""
+    return problem(nx, ny, nu, alpha, [PERIODIC, PERIODIC, dirichlet(Tc), dirichlet(Th, U)], Q=Q)
+
+
+# Sizes of the workloads named in the benchmark and the tests.
+CHANNEL_64x32 = dict(nx=64, ny=32)
+CAVITY_256 = dict(n=256, Ra=1e5, Pr=0.71)
+CAVITY_4096 = dict(n=4096, Ra=1e6, Pr=0.71, Q=5e-6)
+CAVITY_512_STANDIN = dict(n=512, Ra=1e6, Pr=0.71, Q=5e-6)
+
+
+def large_cavity(n=4096):
+    return cavity(n, Ra=1e6, Pr=0.71, Q=5e-6)
+
+
+# --------------------------------------------------------------------------
+# Batched sweep: many cavities of uneven size and parameters
+# --------------------------------------------------------------------------
+
+SWEEP_SIDES = list(range(64, 513, 32))
+
+
+def sweep(count=256, seed=2024, sides=SWEEP_SIDES, ra_range=(1e3, 1e6), pr_range=(0.7, 7.0),
+          q_range=(0.0, 1e-4), U=0.1, tau_max=2.0):
+    """Seeded list of (problem, seed) pairs. Sides a <= b <= 2a drawn from `sides`,
+    orientation by coin flip; Ra log-uniform, Pr and Q uniform. Where the U = 0.1 rule
+    would give a relaxation time above tau_max the characteristic velocity is lowered
+    so that nu = (tau_max - 1/2)/3."""
+    u = uniform01(seed, count * 8).reshape(count, 8)
+    pairs = [(a, b) for a in sides for b in sides if a <= b <= 2 * a]
+    out = []
+    for k in range(count):
+        a, b = pairs[min(int(u[k, 0] * len(pairs)), len(pairs) - 1)]
+        nx, ny = (a, b) if u[k, 1] < 0.5 else (b, a)
+        Ra = 10.0 ** (math.log10(ra_range[0]) + u[k, 2] * (math.log10(ra_range[1]) - math.log10(ra_range[0])))
+        Pr = pr_range[0] + u[k, 3] * (pr_range[1] - pr_range[0])
+        Q = q_range[0] + u[k, 4] * (q_range[1] - q_range[0])
+        Uk = U
+        nu = Uk * ny * math.sqrt(Pr / Ra)
+        nu_max = (tau_max - 0.5) / 3.0
+        if nu > nu_max:
+            Uk = U * nu_max / nu
+        prob = cavity(nx, ny, Ra=Ra, Pr=Pr, Q=Q, U=Uk)
+        prob["meta"] = {"Ra": Ra, "Pr": Pr, "U": Uk}
+        out.append((prob, int(seed * 1000 + k)))
+    return out
