@@ -1,0 +1,229 @@
+/*
+ * clbm.h -- C ABI of the MI355X (gfx950) library for the thermal cascaded
+ * lattice Boltzmann method of Fei & Luo, "Cascaded lattice Boltzmann method
+ * for incompressible thermal flows with heat sources and general thermal
+ * boundary conditions" (arXiv:1801.04577).
+ *
+ * What one time step computes (clbm_step), per lattice node, fused in one
+ * kernel launch:
+ *   - streaming of the D2Q9 flow populations f_i and the D2Q5 temperature
+ *     populations g_i (Eq. 11, Eq. 21) in pull form;
+ *   - half-way bounce-back of f at no-slip walls (Sec. 3), with the
+ *     momentum-exchange correction for a wall moving tangentially;
+ *   - the general bounce-back scheme for g at thermal walls (Eq. 26), the wall
+ *     temperature from the Robin data b1 dT/dn + b2 T = b3 (Eq. 27-28);
+ *   - temperature with the source correction (Eq. 25), Boussinesq force
+ *     (Eq. 2, gravity along -y), density and velocity (Eq. 12);
+ *   - the cascaded collision of f in central-moment space with the consistent
+ *     force term (Eq. 5-10) and back-transform;
+ *   - the cascaded collision of g with the central-moment heat source (Eq. 13-20,
+ *     Eq. 23-24) and back-transform.
+ *
+ * Conventions shared by every call:
+ *   - Memory: the caller owns every device buffer (workspace, fields). The
+ *     library never allocates device memory. Pointers named d_* are device
+ *     pointers; all other pointers are host pointers.
+ *   - Fields: float32, row-major [ny][nx], x fastest (a contiguous
+ *     torch.empty(ny, nx) tensor).
+ *   - Streams: every call enqueues on the HIP stream given at creation
+ *     (hipStream_t passed as void*; NULL is the default stream). Only calls
+ *     documented as synchronising wait for the stream.
+ *   - Time level: the state after n steps is the post-collision state at
+ *     time n; fields and diagnostics report the pre-collision macroscopic
+ *     values at time n (they are collision invariants, up to the F/2 and Q/2
+ *     corrections of Eq. 12 and Eq. 25).
+ *   - Errors: every call returns a clbm_status; nothing is thrown across the
+ *     ABI. A failing call leaves the handle usable unless it reports CLBM_ERR_HIP.
+ *   - Threading: a handle is used from one host thread at a time.
+ */
+#ifndef CLBM_H
+#define CLBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CLBM_ABI_VERSION 1
+
+typedef enum {
+    CLBM_OK = 0,
+    CLBM_ERR_INVALID_ARG = -1,      /* bad pointer, size, side combination, NaN input */
+    CLBM_ERR_UNSTABLE_PARAMS = -2,  /* a relaxation rate outside (0, 2) */
+    CLBM_ERR_BUFFER_TOO_SMALL = -3, /* workspace smaller than clbm_workspace_bytes */
+    CLBM_ERR_HIP = -4,              /* a HIP runtime call failed */
+    CLBM_ERR_NAN = -5,              /* non-finite values found by the diagnostics */
+    CLBM_ERR_UNSUPPORTED = -6       /* option not available for this configuration */
+} clbm_status;
+
+/* Population storage. Both store deviations from the rest state
+ * (f_i - w_i and g_i - T0/5); the arithmetic is float32 in both. */
+typedef enum { CLBM_FP32 = 0, CLBM_FP16_SHIFTED = 1 } clbm_precision;
+
+typedef enum { CLBM_PERIODIC = 0, CLBM_WALL = 1 } clbm_side_kind;
+
+/* Side indices of clbm_params.side. Opposite sides must have the same kind. */
+enum { CLBM_SIDE_XM = 0, CLBM_SIDE_XP = 1, CLBM_SIDE_YM = 2, CLBM_SIDE_YP = 3 };
+
+typedef struct {
+    int kind;       /* clbm_side_kind */
+    double u_wall;  /* tangential wall speed (x- and x+: along y; y- and y+: along x) */
+    double b1, b2, b3; /* thermal wall: b1 dT/dn + b2 T = b3, n the outward normal
+                          (Dirichlet: 0,1,T_w; adiabatic: 1,0,0); not both b1, b2 zero */
+} clbm_side;
+
+typedef struct {
+    int nx, ny;         /* lattice nodes; >= 2 across walled directions */
+    int precision;      /* clbm_precision */
+    double nu;          /* kinematic viscosity: s_nu = 1/(3 nu + 1/2) (Sec. 2.1) */
+    double alpha;       /* thermal diffusivity: lambda_1 = 1/(alpha/c_T^2 + 1/2) (Sec. 2.2) */
+    double s_b;         /* bulk rate (Eq. 8); NaN -> 1 */
+    double s_4;         /* rate of k22 (Eq. 8); NaN -> 1 */
+    double s_3;         /* rate of k21, k12; NaN -> s_3 = (16 - 8 s_nu)/(8 - s_nu) (Sec. 3) */
+    double lambda_0;    /* rate of the thermal k00; it has no effect (NaN -> 1) */
+    double lambda_2;    /* rate of thermal k20, k02; NaN -> 12(lambda_1 - 2)/(lambda_1 - 12) (Sec. 3.1) */
+    double g_beta;      /* Boussinesq: F_y += g_beta (T - T0) (Eq. 2) */
+    double T0;          /* Boussinesq reference temperature; also the storage shift of g */
+    double Fx, Fy;      /* external body force F_v (Eq. 2) */
+    double Q;           /* uniform heat source (Eq. 24) */
+    clbm_side side[4];  /* CLBM_SIDE_XM, _XP, _YM, _YP */
+} clbm_params;
+
+/* Kernel launch shape of the fused step (set by the autotuner or by hand).
+ * block_x * block_y threads per workgroup (multiple of 64, at most 1024);
+ * rows_per_thread in {1, 2, 4}; xcd_remap != 0 maps consecutive tiles to the
+ * same XCD. A zeroed struct selects the built-in default. */
+typedef struct {
+    int block_x, block_y, rows_per_thread, xcd_remap;
+} clbm_launch;
+
+/* Diagnostics at the current time (Sec. 3.3 Nusselt number and a residual). */
+typedef struct {
+    long step;        /* time level of the state */
+    int K;            /* steps since the previous snapshot (0 if none) */
+    double mass;      /* sum over nodes of rho */
+    double sum_u2;    /* sum |u|^2 */
+    double sum_du2;   /* sum |u - u_snapshot|^2 */
+    double sum_T2;    /* sum T^2 */
+    double sum_dT2;   /* sum (T - T_snapshot)^2 */
+    double res_u;     /* sqrt(sum_du2/sum_u2)/K, 0 if K == 0 or sum_u2 == 0 */
+    double res_T;     /* sqrt(sum_dT2/sum_T2)/K, same convention */
+    double dTdn[4];   /* per side: mean outward normal derivative of T at the wall (Eq. 27) */
+    double T_wall[4]; /* per side: mean wall temperature (Eq. 28) */
+    long nan_count;   /* nodes with a non-finite rho, u or T */
+} clbm_diag;
+
+typedef struct clbm_handle clbm_handle;
+
+int clbm_abi_version(void);
+const char* clbm_status_string(int status);
+
+/* Host only. out = {s_nu, s_b, s_3, s_4, lambda_0, lambda_1, lambda_2}: the relaxation
+ * rates the kernels use (Eq. 8, Sec. 2.2, the rules of Sec. 3 and Sec. 3.1). */
+clbm_status clbm_derive_rates(const clbm_params* p, double out[7]);
+
+/* Host only. Validates p and returns the workspace size the handle needs: two
+ * population buffers (14 planes each, rows padded to 64 elements), a snapshot of
+ * (u_x, u_y, T) for the residual, and reduction scratch. */
+clbm_status clbm_workspace_bytes(const clbm_params* p, size_t* bytes);
+
+/* Creates a handle over the caller's workspace (device memory of at least
+ * clbm_workspace_bytes, 256-byte aligned). The state is the rest state
+ * rho = 1, u = 0, T = T0 until clbm_init_from_fields is called. */
+clbm_status clbm_create(const clbm_params* p, void* d_workspace, size_t bytes, void* hip_stream,
+                        clbm_handle** out);
+void clbm_destroy(clbm_handle* h);
+
+/* Initial state: the discrete equilibrium of Eq. (9) and Eq. (19) at the given
+ * (rho, u, T), followed by one collision. Any NULL field takes rho = 1, u = 0,
+ * T = T0. Resets the step counter and the residual snapshot. Asynchronous. */
+clbm_status clbm_init_from_fields(clbm_handle* h, const float* d_rho, const float* d_ux,
+                                  const float* d_uy, const float* d_T);
+
+/* Advances nsteps time steps (one fused kernel per step; steps are replayed from
+ * a HIP graph when graphs are enabled). Asynchronous. */
+clbm_status clbm_step(clbm_handle* h, int nsteps);
+
+/* Writes rho, u_x, u_y, T at the current time; NULL outputs are skipped. Asynchronous. */
+clbm_status clbm_macros(clbm_handle* h, float* d_rho, float* d_ux, float* d_uy, float* d_T);
+
+/* Writes the stored post-collision state as float32 deviations: d_f [9][ny][nx]
+ * holds f*_i - w_i (w = 4/9, 1/9, 1/36), d_g [5][ny][nx] holds g*_i - T0/5.
+ * NULL outputs are skipped. Asynchronous. */
+clbm_status clbm_populations(clbm_handle* h, float* d_f, float* d_g);
+
+/* Reduces the diagnostics over the lattice (wavefront and workgroup reductions,
+ * then a fixed-order FP64 pass) and replaces the residual snapshot with the current
+ * fields. Synchronises the stream. Returns CLBM_ERR_NAN (with *out filled) when a
+ * non-finite value is found. */
+clbm_status clbm_diagnostics(clbm_handle* h, clbm_diag* out);
+
+/* Checkpoint: the state occupies clbm_state_bytes; save copies it to d_dst,
+ * load copies it back and sets the step counter. Asynchronous. */
+clbm_status clbm_state_bytes(const clbm_handle* h, size_t* bytes);
+clbm_status clbm_save(clbm_handle* h, void* d_dst);
+clbm_status clbm_load(clbm_handle* h, const void* d_src, long step);
+
+clbm_status clbm_get_step(const clbm_handle* h, long* step);
+clbm_status clbm_set_launch(clbm_handle* h, const clbm_launch* launch);
+clbm_status clbm_get_launch(const clbm_handle* h, clbm_launch* launch);
+/* steps_per_graph = 0 launches every step on the stream; an even value > 0 replays
+ * graphs of that many steps (the default is 0). */
+clbm_status clbm_set_graph(clbm_handle* h, int steps_per_graph);
+
+/* ------------------------------------------------------------------------ */
+/* Batched form: many independent lattices (each with its own size and        */
+/* parameters) advanced together, one kernel launch per time step over a      */
+/* device tile list covering every active instance.                            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct clbm_batch clbm_batch;
+
+/* Status codes per instance reported by clbm_batch_run. */
+enum { CLBM_INST_RUNNING = 0, CLBM_INST_CONVERGED = 1, CLBM_INST_DIVERGED = 2,
+       CLBM_INST_MAX_STEPS = 3 };
+
+/* Tile shape of the batched kernel: tile_x * tile_y nodes per workgroup, one node
+ * per thread (tile_x a multiple of 64, tile_x * tile_y <= 1024). persistent_wgs > 0
+ * launches that many workgroups, each looping over tiles; 0 launches one workgroup
+ * per tile. */
+typedef struct {
+    int tile_x, tile_y, persistent_wgs;
+} clbm_batch_launch;
+
+/* Host only. Workspace for n instances (all precision fields must be CLBM_FP32). */
+clbm_status clbm_batch_workspace_bytes(int n, const clbm_params* p, size_t* bytes);
+/* launch NULL selects the default shape. */
+clbm_status clbm_batch_create(int n, const clbm_params* p, void* d_workspace, size_t bytes,
+                              void* hip_stream, const clbm_batch_launch* launch,
+                              clbm_batch** out);
+void clbm_batch_destroy(clbm_batch* b);
+/* Initial state of instance i from its fields (NULL: rest state), as clbm_init_from_fields. */
+clbm_status clbm_batch_init(clbm_batch* b, int i, const float* d_rho, const float* d_ux,
+                            const float* d_uy, const float* d_T);
+/* Advances every active instance by nsteps (asynchronous). */
+clbm_status clbm_batch_step(clbm_batch* b, int nsteps);
+/* Runs until every instance has converged (max(res_u, res_T) < tol, residuals over
+ * windows of K steps), diverged (non-finite value or |u| > 0.5) or reached max_steps.
+ * Convergence checks and retirement of instances run on the device inside a replayed
+ * HIP graph of K steps. Synchronises. steps_out[i] is the step at which instance i
+ * stopped, status_out[i] its CLBM_INST_* code; both host arrays of length n. */
+clbm_status clbm_batch_run(clbm_batch* b, long max_steps, double tol, int K, long* steps_out,
+                           int* status_out);
+clbm_status clbm_batch_macros(clbm_batch* b, int i, float* d_rho, float* d_ux, float* d_uy,
+                              float* d_T);
+/* Host copy of instance i's last residuals {res_u, res_T}; synchronises. */
+clbm_status clbm_batch_residual(clbm_batch* b, int i, double out[2]);
+/* Times candidate tile shapes on the batch's own instances (each for `steps` steps
+ * after a 2-step warm-up), keeps the fastest, and appends one JSON line per candidate
+ * to cache_path when it is not NULL. Every timed step advances the instances, so call
+ * it before clbm_batch_init (or re-initialise afterwards). Synchronises. */
+clbm_status clbm_batch_autotune(clbm_batch* b, int steps, const char* cache_path,
+                                clbm_batch_launch* best);
+clbm_status clbm_batch_set_launch(clbm_batch* b, const clbm_batch_launch* launch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

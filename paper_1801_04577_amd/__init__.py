@@ -1,0 +1,417 @@
+"""Python binding of libclbm.so, the gfx950 library for the thermal cascaded LBM of
+Fei & Luo (arXiv:1801.04577).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``csrc/`` behind the C ABI declared in ``include/clbm.h``. PyTorch supplies
+device memory (the workspace and field tensors) and the HIP stream. The
+functions below carry the C names; ``Solver`` and ``Batch`` are small
+conveniences over them.
+
+There is no fallback: if ``libclbm.so`` has not been built, loading fails.
+"""
+import ctypes
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libclbm.so")
+
+CLBM_OK = 0
+CLBM_ERR_NAN = -5
+CLBM_FP32 = 0
+CLBM_FP16_SHIFTED = 1
+_KIND = {"periodic": 0, "wall": 1}
+INST_STATUS = {0: "running", 1: "converged", 2: "diverged", 3: "max_steps"}
+
+
+class ClbmError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__("%s failed: %s (status %d)" % (what, status_string(status), status))
+
+
+class clbm_side(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("u_wall", ctypes.c_double), ("b1", ctypes.c_double),
+                ("b2", ctypes.c_double), ("b3", ctypes.c_double)]
+
+
+class clbm_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("precision", ctypes.c_int),
+        ("nu", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("s_b", ctypes.c_double), ("s_4", ctypes.c_double), ("s_3", ctypes.c_double),
+        ("lambda_0", ctypes.c_double), ("lambda_2", ctypes.c_double),
+        ("g_beta", ctypes.c_double), ("T0", ctypes.c_double),
+        ("Fx", ctypes.c_double), ("Fy", ctypes.c_double), ("Q", ctypes.c_double),
+        ("side", clbm_side * 4),
+    ]
+
+
+class clbm_launch(ctypes.Structure):
+    _fields_ = [("block_x", ctypes.c_int), ("block_y", ctypes.c_int),
+                ("rows_per_thread", ctypes.c_int), ("xcd_remap", ctypes.c_int)]
+
+
+class clbm_diag(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_long), ("K", ctypes.c_int), ("mass", ctypes.c_double),
+        ("sum_u2", ctypes.c_double), ("sum_du2", ctypes.c_double), ("sum_T2", ctypes.c_double),
+        ("sum_dT2", ctypes.c_double), ("res_u", ctypes.c_double), ("res_T", ctypes.c_double),
+        ("dTdn", ctypes.c_double * 4), ("T_wall", ctypes.c_double * 4), ("nan_count", ctypes.c_long),
+    ]
+
+    def as_dict(self):
+        return {"step": self.step, "K": self.K, "mass": self.mass, "sum_u2": self.sum_u2,
+                "sum_du2": self.sum_du2, "sum_T2": self.sum_T2, "sum_dT2": self.sum_dT2,
+                "res_u": self.res_u, "res_T": self.res_T, "dTdn": list(self.dTdn),
+                "T_wall": list(self.T_wall), "nan_count": self.nan_count}
+
+
+class clbm_batch_launch(ctypes.Structure):
+    _fields_ = [("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int), ("persistent_wgs", ctypes.c_int)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_FP = ctypes.c_void_p  # device float* passed as integer addresses
+
+
+def _declare(L):
+    P = ctypes.POINTER(clbm_params)
+    st = ctypes.c_int
+    sig = {
+        "clbm_abi_version": (ctypes.c_int, []),
+        "clbm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "clbm_derive_rates": (st, [P, ctypes.POINTER(ctypes.c_double)]),
+        "clbm_workspace_bytes": (st, [P, ctypes.POINTER(ctypes.c_size_t)]),
+        "clbm_create": (st, [P, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+        "clbm_destroy": (None, [_VP]),
+        "clbm_init_from_fields": (st, [_VP, _FP, _FP, _FP, _FP]),
+        "clbm_step": (st, [_VP, ctypes.c_int]),
+        "clbm_macros": (st, [_VP, _FP, _FP, _FP, _FP]),
+        "clbm_populations": (st, [_VP, _FP, _FP]),
+        "clbm_diagnostics": (st, [_VP, ctypes.POINTER(clbm_diag)]),
+        "clbm_state_bytes": (st, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
+        "clbm_save": (st, [_VP, _VP]),
+        "clbm_load": (st, [_VP, _VP, ctypes.c_long]),
+        "clbm_get_step": (st, [_VP, ctypes.POINTER(ctypes.c_long)]),
+        "clbm_set_launch": (st, [_VP, ctypes.POINTER(clbm_launch)]),
+        "clbm_get_launch": (st, [_VP, ctypes.POINTER(clbm_launch)]),
+        "clbm_set_graph": (st, [_VP, ctypes.c_int]),
+        "clbm_batch_workspace_bytes": (st, [ctypes.c_int, P, ctypes.POINTER(ctypes.c_size_t)]),
+        "clbm_batch_create": (st, [ctypes.c_int, P, _VP, ctypes.c_size_t, _VP,
+                                   ctypes.POINTER(clbm_batch_launch), ctypes.POINTER(_VP)]),
+        "clbm_batch_destroy": (None, [_VP]),
+        "clbm_batch_init": (st, [_VP, ctypes.c_int, _FP, _FP, _FP, _FP]),
+        "clbm_batch_step": (st, [_VP, ctypes.c_int]),
+        "clbm_batch_run": (st, [_VP, ctypes.c_long, ctypes.c_double, ctypes.c_int,
+                                ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_int)]),
+        "clbm_batch_macros": (st, [_VP, ctypes.c_int, _FP, _FP, _FP, _FP]),
+        "clbm_batch_residual": (st, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+        "clbm_batch_autotune": (st, [_VP, ctypes.c_int, ctypes.c_char_p,
+                                     ctypes.POINTER(clbm_batch_launch)]),
+        "clbm_batch_set_launch": (st, [_VP, ctypes.POINTER(clbm_batch_launch)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name, None)
+        if fn is None:
+            continue
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+def lib():
+    """Load libclbm.so. Raises if it has not been built (no CPU fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise ImportError("libclbm.so is not built; run paper_1801_04577_amd/build.py "
+                              "(or __graft_entry__.build())")
+        _lib = _declare(ctypes.CDLL(LIBPATH))
+    return _lib
+
+
+def ensure_built():
+    """Build the library only if it is missing, then load it."""
+    if not os.path.exists(LIBPATH):
+        from . import build as _build
+        _build.build()
+    return lib()
+
+
+def status_string(status):
+    try:
+        return lib().clbm_status_string(int(status)).decode()
+    except Exception:
+        return "status %d" % status
+
+
+def _check(status, what):
+    if status != CLBM_OK:
+        raise ClbmError(status, what)
+
+
+def _nan_if_none(v):
+    return float("nan") if v is None else float(v)
+
+
+def make_params(prob, precision=CLBM_FP32):
+    """clbm_params from a problem dict (see workloads/) -- marshalling only."""
+    p = clbm_params()
+    p.nx, p.ny = int(prob["nx"]), int(prob["ny"])
+    p.precision = int(precision)
+    p.nu, p.alpha = float(prob["nu"]), float(prob["alpha"])
+    for k in ("s_b", "s_4", "s_3", "lambda_0", "lambda_2"):
+        setattr(p, k, _nan_if_none(prob.get(k)))
+    for k in ("g_beta", "T0", "Fx", "Fy", "Q"):
+        setattr(p, k, float(prob.get(k, 0.0)))
+    for s, side in enumerate(prob["sides"]):
+        p.side[s].kind = _KIND[side["kind"]]
+        p.side[s].u_wall = float(side.get("u_wall", 0.0))
+        p.side[s].b1 = float(side.get("b1", 0.0))
+        p.side[s].b2 = float(side.get("b2", 1.0))
+        p.side[s].b3 = float(side.get("b3", 0.0))
+    return p
+
+
+def _addr(t):
+    return None if t is None else ctypes.c_void_p(int(t.data_ptr()))
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(int(s.cuda_stream))
+
+
+# ---------------------------------------------------------------------------
+# C-named wrappers
+# ---------------------------------------------------------------------------
+
+def clbm_abi_version():
+    return lib().clbm_abi_version()
+
+
+def clbm_derive_rates(params):
+    out = (ctypes.c_double * 7)()
+    _check(lib().clbm_derive_rates(ctypes.byref(params), out), "clbm_derive_rates")
+    return list(out)
+
+
+def clbm_workspace_bytes(params):
+    n = ctypes.c_size_t()
+    _check(lib().clbm_workspace_bytes(ctypes.byref(params), ctypes.byref(n)), "clbm_workspace_bytes")
+    return n.value
+
+
+def clbm_batch_workspace_bytes(params_list):
+    arr = (clbm_params * len(params_list))(*params_list)
+    n = ctypes.c_size_t()
+    _check(lib().clbm_batch_workspace_bytes(len(params_list), arr, ctypes.byref(n)),
+           "clbm_batch_workspace_bytes")
+    return n.value
+
+
+def _workspace(nbytes, device):
+    import torch
+    # 256-byte aligned by the caching allocator; keep the tensor alive with the handle.
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+class Solver:
+    """One lattice on the GPU. Fields are torch float32 tensors [ny][nx] on the device."""
+
+    def __init__(self, prob, precision=CLBM_FP32, device="cuda", stream=None):
+        import torch
+        self.prob = prob
+        self.nx, self.ny = int(prob["nx"]), int(prob["ny"])
+        self.device = torch.device(device)
+        self.params = make_params(prob, precision)
+        self.precision = precision
+        L = lib()
+        self.workspace = _workspace(clbm_workspace_bytes(self.params), self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(L.clbm_create(ctypes.byref(self.params), _addr(self.workspace),
+                             self.workspace.numel(), _stream_ptr(self.stream), ctypes.byref(h)),
+               "clbm_create")
+        self._h = h
+
+    def _f(self, a):
+        import torch
+        if a is None:
+            return None
+        t = torch.as_tensor(a, dtype=torch.float32, device=self.device)
+        t = t.expand(self.ny, self.nx).contiguous() if t.dim() < 2 else t.contiguous()
+        assert tuple(t.shape) == (self.ny, self.nx), t.shape
+        return t
+
+    def init(self, rho=None, ux=None, uy=None, T=None):
+        fs = [self._f(a) for a in (rho, ux, uy, T)]
+        _check(lib().clbm_init_from_fields(self._h, *[_addr(t) for t in fs]), "clbm_init_from_fields")
+        self._keep = fs  # the kernel reads them asynchronously
+
+    def step(self, n=1):
+        _check(lib().clbm_step(self._h, int(n)), "clbm_step")
+
+    @property
+    def t(self):
+        v = ctypes.c_long()
+        _check(lib().clbm_get_step(self._h, ctypes.byref(v)), "clbm_get_step")
+        return v.value
+
+    def macros(self):
+        import torch
+        out = [torch.empty(self.ny, self.nx, dtype=torch.float32, device=self.device) for _ in range(4)]
+        _check(lib().clbm_macros(self._h, *[_addr(t) for t in out]), "clbm_macros")
+        return tuple(out)
+
+    def populations(self):
+        """Post-collision deviations (f* - w [9][ny][nx], g* - T0/5 [5][ny][nx])."""
+        import torch
+        f = torch.empty(9, self.ny, self.nx, dtype=torch.float32, device=self.device)
+        g = torch.empty(5, self.ny, self.nx, dtype=torch.float32, device=self.device)
+        _check(lib().clbm_populations(self._h, _addr(f), _addr(g)), "clbm_populations")
+        return f, g
+
+    def diagnostics(self, raise_on_nan=False):
+        d = clbm_diag()
+        st = lib().clbm_diagnostics(self._h, ctypes.byref(d))
+        if st == CLBM_ERR_NAN and not raise_on_nan:
+            return d
+        _check(st, "clbm_diagnostics")
+        return d
+
+    def state_bytes(self):
+        n = ctypes.c_size_t()
+        _check(lib().clbm_state_bytes(self._h, ctypes.byref(n)), "clbm_state_bytes")
+        return n.value
+
+    def save(self):
+        import torch
+        buf = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        _check(lib().clbm_save(self._h, _addr(buf)), "clbm_save")
+        return buf, self.t
+
+    def load(self, buf, step):
+        _check(lib().clbm_load(self._h, _addr(buf), int(step)), "clbm_load")
+
+    def set_launch(self, block_x=256, block_y=1, rows_per_thread=1, xcd_remap=0):
+        L = clbm_launch(int(block_x), int(block_y), int(rows_per_thread), int(xcd_remap))
+        _check(lib().clbm_set_launch(self._h, ctypes.byref(L)), "clbm_set_launch")
+
+    def get_launch(self):
+        L = clbm_launch()
+        _check(lib().clbm_get_launch(self._h, ctypes.byref(L)), "clbm_get_launch")
+        return {"block_x": L.block_x, "block_y": L.block_y, "rows_per_thread": L.rows_per_thread,
+                "xcd_remap": L.xcd_remap}
+
+    def set_graph(self, steps_per_graph):
+        _check(lib().clbm_set_graph(self._h, int(steps_per_graph)), "clbm_set_graph")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().clbm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many lattices (own sizes and parameters) advanced together on the GPU."""
+
+    def __init__(self, probs, device="cuda", stream=None, launch=None):
+        import torch
+        self.probs = list(probs)
+        self.n = len(self.probs)
+        self.device = torch.device(device)
+        self.params = (clbm_params * self.n)(*[make_params(p) for p in self.probs])
+        nbytes = ctypes.c_size_t()
+        _check(lib().clbm_batch_workspace_bytes(self.n, self.params, ctypes.byref(nbytes)),
+               "clbm_batch_workspace_bytes")
+        self.workspace = _workspace(nbytes.value, self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        L = None
+        if launch:
+            L = clbm_batch_launch(int(launch["tile_x"]), int(launch["tile_y"]),
+                                  int(launch.get("persistent_wgs", 0)))
+        h = ctypes.c_void_p()
+        _check(lib().clbm_batch_create(self.n, self.params, _addr(self.workspace),
+                                       self.workspace.numel(), _stream_ptr(self.stream),
+                                       ctypes.byref(L) if L is not None else None, ctypes.byref(h)),
+               "clbm_batch_create")
+        self._h = h
+        self._keep = {}
+
+    def init(self, i, rho=None, ux=None, uy=None, T=None):
+        import torch
+        nx, ny = int(self.probs[i]["nx"]), int(self.probs[i]["ny"])
+        fs = []
+        for a in (rho, ux, uy, T):
+            if a is None:
+                fs.append(None)
+                continue
+            t = torch.as_tensor(a, dtype=torch.float32, device=self.device)
+            t = t.expand(ny, nx).contiguous() if t.dim() < 2 else t.contiguous()
+            assert tuple(t.shape) == (ny, nx), t.shape
+            fs.append(t)
+        _check(lib().clbm_batch_init(self._h, int(i), *[_addr(t) for t in fs]), "clbm_batch_init")
+        self._keep[i] = fs
+
+    def step(self, n=1):
+        _check(lib().clbm_batch_step(self._h, int(n)), "clbm_batch_step")
+
+    def run(self, max_steps, tol, K=1000):
+        """Returns (steps, status) per instance; status names from INST_STATUS."""
+        steps = (ctypes.c_long * self.n)()
+        status = (ctypes.c_int * self.n)()
+        _check(lib().clbm_batch_run(self._h, int(max_steps), float(tol), int(K), steps, status),
+               "clbm_batch_run")
+        return list(steps), [INST_STATUS[s] for s in status]
+
+    def macros(self, i):
+        import torch
+        nx, ny = int(self.probs[i]["nx"]), int(self.probs[i]["ny"])
+        out = [torch.empty(ny, nx, dtype=torch.float32, device=self.device) for _ in range(4)]
+        _check(lib().clbm_batch_macros(self._h, int(i), *[_addr(t) for t in out]), "clbm_batch_macros")
+        return tuple(out)
+
+    def residual(self, i):
+        out = (ctypes.c_double * 2)()
+        _check(lib().clbm_batch_residual(self._h, int(i), out), "clbm_batch_residual")
+        return out[0], out[1]
+
+    def set_launch(self, tile_x, tile_y, persistent_wgs=0):
+        L = clbm_batch_launch(int(tile_x), int(tile_y), int(persistent_wgs))
+        _check(lib().clbm_batch_set_launch(self._h, ctypes.byref(L)), "clbm_batch_set_launch")
+
+    def autotune(self, steps=20, cache_path=None):
+        best = clbm_batch_launch()
+        path = cache_path.encode() if cache_path else None
+        _check(lib().clbm_batch_autotune(self._h, int(steps), path, ctypes.byref(best)),
+               "clbm_batch_autotune")
+        return {"tile_x": best.tile_x, "tile_y": best.tile_y, "persistent_wgs": best.persistent_wgs}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().clbm_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nusselt(diag, side, H, dT, into_wall=True):
+    """Average Nusselt number at one wall from the mean outward gradient of Eq. (27).
+    into_wall=True: heat flowing from the fluid into the wall (a cold wall),
+    -dT/dn * H/dT; into_wall=False: heat entering the fluid (a hot wall)."""
+    q = -diag.dTdn[side] * H / dT
+    return q if into_wall else -q

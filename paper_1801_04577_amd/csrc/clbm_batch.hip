@@ -1,0 +1,694 @@
+// clbm_batch.hip -- many independent lattices (sizes and parameters per instance)
+// advanced together: one kernel launch per time step walks a device list of
+// (instance, tile) entries covering every running instance. Convergence checks,
+// retirement of converged or diverged instances and compaction of the tile list
+// run on the device, between the steps of a replayed HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "clbm_host.h"
+#include "clbm_kernels.h"
+
+namespace clbm {
+
+struct BatchInst {
+    LatticeConst c;
+    unsigned long long buf[2];  // device addresses of the two population buffers
+    unsigned long long snap;    // device address of the (u_x, u_y, T) snapshot
+    int tiles_x, tile_off, tile_count, pad;
+};
+
+constexpr int kBP = 6;  // per-tile partials: du2, u2, dT2, T2, bad, max|u|
+
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// One time step of every instance on the active tile list (grid-stride over tiles).
+__global__ void __launch_bounds__(1024) k_batch_step(const BatchInst* __restrict__ insts,
+                                                     const int2* __restrict__ list,
+                                                     const int* __restrict__ count, int parity,
+                                                     int tile_x, int tile_y)
+{
+    const int n = uniform_int(*count);
+    for (int t = blockIdx.x; t < n; t += gridDim.x) {
+        const int2 e = list[t];
+        const int inst = uniform_int(e.x), tile = uniform_int(e.y);
+        const BatchInst& I = insts[inst];
+        const LatticeConst c = I.c;
+        const int tiles_x = uniform_int(I.tiles_x);
+        const int x = (tile % tiles_x) * tile_x + threadIdx.x;
+        const int y = (tile / tiles_x) * tile_y + threadIdx.y;
+        if (x < c.nx && y < c.ny) {
+            const float* src = reinterpret_cast<const float*>(I.buf[parity]);
+            float* dst = reinterpret_cast<float*>(I.buf[parity ^ 1]);
+            float a[9], b[5];
+            double tb[5];
+            gather_node(src, c, x, y, a, b);
+            NodeMacro m;
+            collide(c, a, b, tb, m);
+            store_node(dst, c, (unsigned)y * c.pitch + x, a, tb);
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max_d(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    return v;
+}
+
+// Residual partials per active tile (compared with the snapshot when compare != 0),
+// then the snapshot is replaced by the current fields. Partials go to the tile's
+// fixed slot (its index in the full list), so the per-instance sums are formed in a
+// fixed order by k_batch_finalize.
+__global__ void __launch_bounds__(1024) k_batch_diag(const BatchInst* __restrict__ insts,
+                                                     const int2* __restrict__ list,
+                                                     const int* __restrict__ count, int parity,
+                                                     int tile_x, int tile_y, int compare,
+                                                     double* __restrict__ part)
+{
+    __shared__ double lds[16][kBP];
+    const int n = uniform_int(*count);
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = (blockDim.x * blockDim.y + 63) >> 6;
+    for (int t = blockIdx.x; t < n; t += gridDim.x) {
+        const int2 e = list[t];
+        const int inst = uniform_int(e.x), tile = uniform_int(e.y);
+        const BatchInst& I = insts[inst];
+        const LatticeConst c = I.c;
+        const int tiles_x = uniform_int(I.tiles_x);
+        const int x = (tile % tiles_x) * tile_x + threadIdx.x;
+        const int y = (tile / tiles_x) * tile_y + threadIdx.y;
+        double acc[kBP] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (x < c.nx && y < c.ny) {
+            const float* src = reinterpret_cast<const float*>(I.buf[parity]);
+            float* snap = reinterpret_cast<float*>(I.snap);
+            float a[9], b[5];
+            load_own(src, c, (unsigned)y * c.pitch + x, a, b);
+            const NodeMacro m = macros_from_post(c, a, b);
+            const float T = c.T0 + m.theta;
+            const size_t k = (size_t)y * c.nx + x, np = (size_t)c.nx * c.ny;
+            const double u2 = (double)m.ux * m.ux + (double)m.uy * m.uy;
+            if (compare) {
+                const double dx = m.ux - snap[k], dy = m.uy - snap[np + k], dt = T - snap[2 * np + k];
+                acc[0] = dx * dx + dy * dy;
+                acc[2] = dt * dt;
+            }
+            acc[1] = u2;
+            acc[3] = (double)T * T;
+            const bool ok = isfinite(m.drho) && isfinite(m.ux) && isfinite(m.uy) && isfinite(T);
+            acc[4] = ok ? 0.0 : 1.0;
+            acc[5] = ok ? sqrt(u2) : 1e30;
+            snap[k] = m.ux;
+            snap[np + k] = m.uy;
+            snap[2 * np + k] = T;
+        }
+#pragma unroll
+        for (int q = 0; q < kBP; ++q) {
+            const double v = q == 5 ? wave_max_d(acc[q]) : wave_sum_d(acc[q]);
+            if (lane == 0) lds[wave][q] = v;
+        }
+        __syncthreads();
+        if (tid < kBP) {
+            double v = 0.0;
+            for (int w = 0; w < nwaves; ++w) v = tid == 5 ? fmax(v, lds[w][tid]) : v + lds[w][tid];
+            part[(size_t)(I.tile_off + tile) * kBP + tid] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// One workgroup per instance: sums its tile partials in order, updates its step count
+// and residuals, and retires it when converged, diverged or out of steps.
+__global__ void __launch_bounds__(256) k_batch_finalize(const BatchInst* __restrict__ insts,
+                                                        const double* __restrict__ part,
+                                                        int* __restrict__ status,
+                                                        long long* __restrict__ steps,
+                                                        double* __restrict__ res, int K, double tol,
+                                                        long long max_steps)
+{
+    const int i = blockIdx.x;
+    if (status[i] != CLBM_INST_RUNNING) return;
+    const BatchInst& I = insts[i];
+    __shared__ double lds[256][kBP];
+    double acc[kBP] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < I.tile_count; t += blockDim.x) {
+        const double* p = part + (size_t)(I.tile_off + t) * kBP;
+        for (int q = 0; q < 5; ++q) acc[q] += p[q];
+        acc[5] = fmax(acc[5], p[5]);
+    }
+    for (int q = 0; q < kBP; ++q) lds[threadIdx.x][q] = acc[q];
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int q = 0; q < kBP; ++q)
+                lds[threadIdx.x][q] = q == 5 ? fmax(lds[threadIdx.x][q], lds[threadIdx.x + s][q])
+                                             : lds[threadIdx.x][q] + lds[threadIdx.x + s][q];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double* r = lds[0];
+        const long long st = steps[i] + K;
+        steps[i] = st;
+        const double ru = r[1] > 0.0 ? sqrt(r[0] / r[1]) / K : 0.0;
+        const double rT = r[3] > 0.0 ? sqrt(r[2] / r[3]) / K : 0.0;
+        res[2 * i] = ru;
+        res[2 * i + 1] = rT;
+        int s = CLBM_INST_RUNNING;
+        if (r[4] > 0.0 || !(r[5] <= 0.5)) s = CLBM_INST_DIVERGED;
+        else if (fmax(ru, rT) < tol) s = CLBM_INST_CONVERGED;
+        else if (st >= max_steps) s = CLBM_INST_MAX_STEPS;
+        status[i] = s;
+    }
+}
+
+// Compaction, phase 1 (one workgroup): exclusive scan of the running instances'
+// tile counts into newoff[] and the new list length into *count.
+__global__ void __launch_bounds__(1024) k_batch_scan(const BatchInst* __restrict__ insts,
+                                                     const int* __restrict__ status, int n,
+                                                     int* __restrict__ newoff, int* __restrict__ count)
+{
+    __shared__ int lds[1024];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += blockDim.x) {
+        const int i = base + threadIdx.x;
+        const int v = (i < n && status[i] == CLBM_INST_RUNNING) ? insts[i].tile_count : 0;
+        lds[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+            const int add = threadIdx.x >= (unsigned)off ? lds[threadIdx.x - off] : 0;
+            __syncthreads();
+            lds[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < n) newoff[i] = carry + lds[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) carry += lds[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = carry;
+}
+
+// Compaction, phase 2: every entry of the full list belonging to a running instance
+// moves to its new place; entries keep their order.
+__global__ void __launch_bounds__(256) k_batch_scatter(const BatchInst* __restrict__ insts,
+                                                       const int* __restrict__ status,
+                                                       const int* __restrict__ newoff,
+                                                       const int2* __restrict__ full, int total,
+                                                       int2* __restrict__ active)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= total) return;
+    const int2 e = full[f];
+    if (status[e.x] != CLBM_INST_RUNNING) return;
+    active[newoff[e.x] + e.y] = e;
+}
+
+__global__ void k_batch_reset(int* __restrict__ status, long long* __restrict__ steps,
+                              double* __restrict__ res, int n, const int2* __restrict__ full,
+                              int total, int2* __restrict__ active, int* __restrict__ count)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) {
+        status[k] = CLBM_INST_RUNNING;
+        steps[k] = 0;
+        res[2 * k] = 0.0;
+        res[2 * k + 1] = 0.0;
+    }
+    if (k < total) active[k] = full[k];
+    if (k == 0) *count = total;
+}
+
+}  // namespace clbm
+
+using namespace clbm;
+
+struct clbm_batch {
+    int n;
+    std::vector<clbm_params> p;
+    std::vector<BatchInst> inst;
+    std::vector<int2> full_host;
+    hipStream_t stream;
+    BatchInst* d_inst;
+    int* d_status;
+    long long* d_steps;
+    double* d_res;
+    int* d_newoff;
+    int* d_count;
+    int2* d_full;
+    int2* d_active;
+    double* d_part;
+    int cap_tiles;
+    int total_tiles;
+    int parity;
+    long step;
+    clbm_batch_launch launch;
+    hipGraph_t graph;
+    hipGraphExec_t gexec;
+    int graph_K;
+    double graph_tol;
+    long graph_max;
+};
+
+namespace {
+
+constexpr int kMinTileX = 64;
+
+struct BatchLayout {
+    size_t inst, status, steps, res, newoff, count, full, active, part, total;
+    std::vector<size_t> buf0, buf1, snap;
+    int cap_tiles;
+};
+
+bool batch_launch_ok(const clbm_batch_launch& L)
+{
+    return L.tile_x >= kMinTileX && L.tile_x % 64 == 0 && L.tile_y >= 1 &&
+           L.tile_x * L.tile_y <= 1024 && L.persistent_wgs >= 0;
+}
+
+clbm_batch_launch default_batch_launch()
+{
+    clbm_batch_launch L;
+    L.tile_x = 64;
+    L.tile_y = 4;
+    L.persistent_wgs = 0;
+    return L;
+}
+
+clbm_status batch_layout(int n, const clbm_params* p, BatchLayout* L)
+{
+    if (n < 1 || !p) return CLBM_ERR_INVALID_ARG;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, kAlign);
+        return o;
+    };
+    long long cap = 0;
+    for (int i = 0; i < n; ++i) {
+        if (p[i].precision != CLBM_FP32) return CLBM_ERR_UNSUPPORTED;
+        clbm_status st = validate(&p[i], nullptr);
+        if (st != CLBM_OK) return st;
+        cap += (long long)((p[i].nx + kMinTileX - 1) / kMinTileX) * p[i].ny;
+    }
+    if (cap >= (1LL << 30)) return CLBM_ERR_UNSUPPORTED;
+    L->cap_tiles = (int)cap;
+    L->inst = take(sizeof(BatchInst) * n);
+    L->status = take(sizeof(int) * n);
+    L->steps = take(sizeof(long long) * n);
+    L->res = take(sizeof(double) * 2 * n);
+    L->newoff = take(sizeof(int) * n);
+    L->count = take(sizeof(int));
+    L->full = take(sizeof(int2) * cap);
+    L->active = take(sizeof(int2) * cap);
+    L->part = take(sizeof(double) * kBP * cap);
+    L->buf0.resize(n);
+    L->buf1.resize(n);
+    L->snap.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const size_t plane = (size_t)row_pitch(p[i].nx) * p[i].ny;
+        L->buf0[i] = take(14 * plane * sizeof(float));
+        L->buf1[i] = take(14 * plane * sizeof(float));
+        L->snap[i] = take(3 * (size_t)p[i].nx * p[i].ny * sizeof(float));
+    }
+    L->total = off;
+    return CLBM_OK;
+}
+
+void drop_batch_graph(clbm_batch* b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+}
+
+// Rebuild the full tile list and the per-instance tile fields for the current shape.
+clbm_status apply_shape(clbm_batch* b)
+{
+    const clbm_batch_launch& L = b->launch;
+    b->full_host.clear();
+    int off = 0;
+    for (int i = 0; i < b->n; ++i) {
+        BatchInst& I = b->inst[i];
+        const int tx = (I.c.nx + L.tile_x - 1) / L.tile_x;
+        const int ty = (I.c.ny + L.tile_y - 1) / L.tile_y;
+        I.tiles_x = tx;
+        I.tile_off = off;
+        I.tile_count = tx * ty;
+        for (int t = 0; t < tx * ty; ++t) b->full_host.push_back(make_int2(i, t));
+        off += tx * ty;
+    }
+    if (off > b->cap_tiles) return CLBM_ERR_INVALID_ARG;
+    b->total_tiles = off;
+    CLBM_HIP(hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BatchInst) * b->n,
+                            hipMemcpyHostToDevice, b->stream));
+    CLBM_HIP(hipMemcpyAsync(b->d_full, b->full_host.data(), sizeof(int2) * off,
+                            hipMemcpyHostToDevice, b->stream));
+    // every instance running, active list = full list
+    const int m = std::max(b->n, b->total_tiles);
+    hipLaunchKernelGGL(k_batch_reset, dim3((m + 255) / 256), dim3(256), 0, b->stream, b->d_status,
+                       b->d_steps, b->d_res, b->n, b->d_full, b->total_tiles, b->d_active, b->d_count);
+    CLBM_HIP(hipGetLastError());
+    CLBM_HIP(hipStreamSynchronize(b->stream));  // host vectors may change after return
+    drop_batch_graph(b);
+    return CLBM_OK;
+}
+
+dim3 step_grid(const clbm_batch* b)
+{
+    const int g = b->launch.persistent_wgs > 0 ? std::min(b->launch.persistent_wgs, b->total_tiles)
+                                                : b->total_tiles;
+    return dim3(std::max(g, 1));
+}
+
+// Adds a kernel node depending on *prev; argument values are copied by the runtime.
+clbm_status add_node(hipGraph_t g, hipGraphNode_t* prev, const void* fn, dim3 grid, dim3 block,
+                     void** args)
+{
+    hipKernelNodeParams kp;
+    std::memset(&kp, 0, sizeof kp);
+    kp.func = const_cast<void*>(fn);
+    kp.gridDim = grid;
+    kp.blockDim = block;
+    kp.kernelParams = args;
+    hipGraphNode_t node;
+    CLBM_HIP(hipGraphAddKernelNode(&node, g, *prev ? prev : nullptr, *prev ? 1 : 0, &kp));
+    *prev = node;
+    return CLBM_OK;
+}
+
+clbm_status launch_batch_steps(clbm_batch* b, int nsteps)
+{
+    const dim3 blk(b->launch.tile_x, b->launch.tile_y);
+    for (int k = 0; k < nsteps; ++k) {
+        hipLaunchKernelGGL(k_batch_step, step_grid(b), blk, 0, b->stream, b->d_inst, b->d_active,
+                           b->d_count, b->parity, b->launch.tile_x, b->launch.tile_y);
+        CLBM_HIP(hipGetLastError());
+        b->parity ^= 1;
+        b->step++;
+    }
+    return CLBM_OK;
+}
+
+clbm_status launch_diag(clbm_batch* b, int compare)
+{
+    const dim3 blk(b->launch.tile_x, b->launch.tile_y);
+    hipLaunchKernelGGL(k_batch_diag, step_grid(b), blk, 0, b->stream, b->d_inst, b->d_active,
+                       b->d_count, b->parity, b->launch.tile_x, b->launch.tile_y, compare, b->d_part);
+    CLBM_HIP(hipGetLastError());
+    return CLBM_OK;
+}
+
+// Graph: K steps, residual partials, per-instance finalize, compaction (scan, scatter).
+clbm_status build_run_graph(clbm_batch* b, int K, double tol, long max_steps)
+{
+    drop_batch_graph(b);
+    hipGraph_t g = nullptr;
+    CLBM_HIP(hipGraphCreate(&g, 0));
+    hipGraphNode_t prev = nullptr;
+    const dim3 blk(b->launch.tile_x, b->launch.tile_y);
+    const dim3 grid = step_grid(b);
+    int parity = b->parity;
+    int tx = b->launch.tile_x, ty = b->launch.tile_y;
+    clbm_status st = CLBM_OK;
+    for (int k = 0; k < K && st == CLBM_OK; ++k) {
+        void* args[] = {&b->d_inst, &b->d_active, &b->d_count, &parity, &tx, &ty};
+        st = add_node(g, &prev, reinterpret_cast<const void*>(&k_batch_step), grid, blk, args);
+        parity ^= 1;
+    }
+    int compare = 1;
+    if (st == CLBM_OK) {
+        void* args[] = {&b->d_inst, &b->d_active, &b->d_count, &parity, &tx, &ty, &compare, &b->d_part};
+        st = add_node(g, &prev, reinterpret_cast<const void*>(&k_batch_diag), grid, blk, args);
+    }
+    long long maxs = max_steps;
+    if (st == CLBM_OK) {
+        void* args[] = {&b->d_inst, &b->d_part, &b->d_status, &b->d_steps, &b->d_res, &K, &tol, &maxs};
+        st = add_node(g, &prev, reinterpret_cast<const void*>(&k_batch_finalize), dim3(b->n),
+                      dim3(256), args);
+    }
+    int n = b->n;
+    if (st == CLBM_OK) {
+        void* args[] = {&b->d_inst, &b->d_status, &n, &b->d_newoff, &b->d_count};
+        st = add_node(g, &prev, reinterpret_cast<const void*>(&k_batch_scan), dim3(1), dim3(1024), args);
+    }
+    int total = b->total_tiles;
+    if (st == CLBM_OK) {
+        void* args[] = {&b->d_inst, &b->d_status, &b->d_newoff, &b->d_full, &total, &b->d_active};
+        st = add_node(g, &prev, reinterpret_cast<const void*>(&k_batch_scatter),
+                      dim3((total + 255) / 256), dim3(256), args);
+    }
+    if (st != CLBM_OK) {
+        (void)hipGraphDestroy(g);
+        return st;
+    }
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        set_last_hip_error(e, "hipGraphInstantiate", __FILE__, __LINE__);
+        return CLBM_ERR_HIP;
+    }
+    b->graph = g;
+    b->gexec = ex;
+    b->graph_K = K;
+    b->graph_tol = tol;
+    b->graph_max = max_steps;
+    return CLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+clbm_status clbm_batch_workspace_bytes(int n, const clbm_params* p, size_t* bytes)
+{
+    if (!bytes) return CLBM_ERR_INVALID_ARG;
+    BatchLayout L;
+    clbm_status st = batch_layout(n, p, &L);
+    if (st != CLBM_OK) return st;
+    *bytes = L.total;
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_create(int n, const clbm_params* p, void* d_workspace, size_t bytes,
+                              void* hip_stream, const clbm_batch_launch* launch, clbm_batch** out)
+{
+    if (!out) return CLBM_ERR_INVALID_ARG;
+    *out = nullptr;
+    BatchLayout L;
+    clbm_status st = batch_layout(n, p, &L);
+    if (st != CLBM_OK) return st;
+    if (!d_workspace || ((uintptr_t)d_workspace) % kAlign != 0) return CLBM_ERR_INVALID_ARG;
+    if (bytes < L.total) return CLBM_ERR_BUFFER_TOO_SMALL;
+    clbm_batch_launch lc = launch ? *launch : default_batch_launch();
+    if (!batch_launch_ok(lc)) return CLBM_ERR_INVALID_ARG;
+    clbm_batch* b = new (std::nothrow) clbm_batch();
+    if (!b) return CLBM_ERR_INVALID_ARG;
+    char* ws = (char*)d_workspace;
+    b->n = n;
+    b->p.assign(p, p + n);
+    b->inst.resize(n);
+    b->stream = (hipStream_t)hip_stream;
+    b->d_inst = (BatchInst*)(ws + L.inst);
+    b->d_status = (int*)(ws + L.status);
+    b->d_steps = (long long*)(ws + L.steps);
+    b->d_res = (double*)(ws + L.res);
+    b->d_newoff = (int*)(ws + L.newoff);
+    b->d_count = (int*)(ws + L.count);
+    b->d_full = (int2*)(ws + L.full);
+    b->d_active = (int2*)(ws + L.active);
+    b->d_part = (double*)(ws + L.part);
+    b->cap_tiles = L.cap_tiles;
+    b->launch = lc;
+    for (int i = 0; i < n; ++i) {
+        Rates r;
+        (void)derive_rates(&p[i], &r);
+        BatchInst& I = b->inst[i];
+        std::memset(&I, 0, sizeof I);
+        I.c = make_const(&p[i], r);
+        I.buf[0] = (unsigned long long)(uintptr_t)(ws + L.buf0[i]);
+        I.buf[1] = (unsigned long long)(uintptr_t)(ws + L.buf1[i]);
+        I.snap = (unsigned long long)(uintptr_t)(ws + L.snap[i]);
+    }
+    st = apply_shape(b);
+    if (st == CLBM_OK)
+        for (int i = 0; i < n && st == CLBM_OK; ++i)
+            st = clbm_batch_init(b, i, nullptr, nullptr, nullptr, nullptr);
+    if (st != CLBM_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return CLBM_OK;
+}
+
+void clbm_batch_destroy(clbm_batch* b)
+{
+    if (!b) return;
+    drop_batch_graph(b);
+    delete b;
+}
+
+clbm_status clbm_batch_init(clbm_batch* b, int i, const float* d_rho, const float* d_ux,
+                            const float* d_uy, const float* d_T)
+{
+    if (!b || i < 0 || i >= b->n) return CLBM_ERR_INVALID_ARG;
+    const BatchInst& I = b->inst[i];
+    const dim3 blk(64, 4);
+    const dim3 grd((I.c.nx + 63) / 64, (I.c.ny + 3) / 4);
+    // the current buffer of the batch (all instances share the parity)
+    hipLaunchKernelGGL(k_init<float>, grd, blk, 0, b->stream, (float*)(uintptr_t)I.buf[b->parity],
+                       I.c, d_rho, d_ux, d_uy, d_T);
+    CLBM_HIP(hipGetLastError());
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_step(clbm_batch* b, int nsteps)
+{
+    if (!b || nsteps < 0) return CLBM_ERR_INVALID_ARG;
+    return launch_batch_steps(b, nsteps);
+}
+
+clbm_status clbm_batch_run(clbm_batch* b, long max_steps, double tol, int K, long* steps_out,
+                           int* status_out)
+{
+    if (!b || K < 2 || (K % 2) != 0 || max_steps < 0 || !(tol >= 0.0)) return CLBM_ERR_INVALID_ARG;
+    // all instances running from the current state; snapshot for the first window
+    const int m = std::max(b->n, b->total_tiles);
+    hipLaunchKernelGGL(k_batch_reset, dim3((m + 255) / 256), dim3(256), 0, b->stream, b->d_status,
+                       b->d_steps, b->d_res, b->n, b->d_full, b->total_tiles, b->d_active, b->d_count);
+    CLBM_HIP(hipGetLastError());
+    clbm_status st = launch_diag(b, 0);
+    if (st != CLBM_OK) return st;
+    if (!b->gexec || b->graph_K != K || b->graph_tol != tol || b->graph_max != max_steps) {
+        st = build_run_graph(b, K, tol, max_steps);
+        if (st != CLBM_OK) return st;
+    }
+    long done = 0;
+    int count = b->total_tiles;
+    while (count > 0 && done < max_steps + K) {
+        CLBM_HIP(hipGraphLaunch(b->gexec, b->stream));
+        b->step += K;
+        done += K;
+        CLBM_HIP(hipMemcpyAsync(&count, b->d_count, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+        CLBM_HIP(hipStreamSynchronize(b->stream));
+    }
+    std::vector<long long> steps(b->n);
+    std::vector<int> status(b->n);
+    CLBM_HIP(hipMemcpyAsync(steps.data(), b->d_steps, sizeof(long long) * b->n,
+                            hipMemcpyDeviceToHost, b->stream));
+    CLBM_HIP(hipMemcpyAsync(status.data(), b->d_status, sizeof(int) * b->n, hipMemcpyDeviceToHost,
+                            b->stream));
+    CLBM_HIP(hipStreamSynchronize(b->stream));
+    for (int i = 0; i < b->n; ++i) {
+        if (steps_out) steps_out[i] = (long)steps[i];
+        if (status_out) status_out[i] = status[i];
+    }
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_macros(clbm_batch* b, int i, float* d_rho, float* d_ux, float* d_uy, float* d_T)
+{
+    if (!b || i < 0 || i >= b->n) return CLBM_ERR_INVALID_ARG;
+    const BatchInst& I = b->inst[i];
+    const dim3 blk(64, 4);
+    const dim3 grd((I.c.nx + 63) / 64, (I.c.ny + 3) / 4);
+    hipLaunchKernelGGL(k_macros<float>, grd, blk, 0, b->stream,
+                       (const float*)(uintptr_t)I.buf[b->parity], I.c, d_rho, d_ux, d_uy, d_T);
+    CLBM_HIP(hipGetLastError());
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_residual(clbm_batch* b, int i, double out[2])
+{
+    if (!b || i < 0 || i >= b->n || !out) return CLBM_ERR_INVALID_ARG;
+    CLBM_HIP(hipMemcpyAsync(out, b->d_res + 2 * i, 2 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    CLBM_HIP(hipStreamSynchronize(b->stream));
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_set_launch(clbm_batch* b, const clbm_batch_launch* launch)
+{
+    if (!b || !launch || !batch_launch_ok(*launch)) return CLBM_ERR_INVALID_ARG;
+    b->launch = *launch;
+    return apply_shape(b);
+}
+
+clbm_status clbm_batch_autotune(clbm_batch* b, int steps, const char* cache_path,
+                                clbm_batch_launch* best)
+{
+    if (!b || steps < 1) return CLBM_ERR_INVALID_ARG;
+    static const int shapes[][2] = {{64, 1}, {64, 2}, {64, 4}, {64, 8}, {128, 1}, {128, 2},
+                                    {128, 4}, {256, 1}, {256, 2}, {256, 4}, {512, 1}, {512, 2}};
+    static const int wgs[] = {0, 2048, 8192};
+    FILE* fp = cache_path ? std::fopen(cache_path, "a") : nullptr;
+    hipEvent_t e0, e1;
+    CLBM_HIP(hipEventCreate(&e0));
+    CLBM_HIP(hipEventCreate(&e1));
+    double best_ms = 1e300;
+    clbm_batch_launch best_L = b->launch;
+    long long nodes = 0;
+    for (int i = 0; i < b->n; ++i) nodes += (long long)b->p[i].nx * b->p[i].ny;
+    clbm_status st = CLBM_OK;
+    for (const auto& sh : shapes) {
+        for (int w : wgs) {
+            clbm_batch_launch L;
+            L.tile_x = sh[0];
+            L.tile_y = sh[1];
+            L.persistent_wgs = w;
+            if (!batch_launch_ok(L)) continue;
+            b->launch = L;
+            st = apply_shape(b);
+            if (st != CLBM_OK) break;
+            if (w > 0 && w >= b->total_tiles) continue;  // same as one workgroup per tile
+            st = launch_batch_steps(b, 2);               // warm-up (even: parity unchanged)
+            if (st != CLBM_OK) break;
+            CLBM_HIP(hipEventRecord(e0, b->stream));
+            st = launch_batch_steps(b, 2 * ((steps + 1) / 2));
+            if (st != CLBM_OK) break;
+            CLBM_HIP(hipEventRecord(e1, b->stream));
+            CLBM_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            CLBM_HIP(hipEventElapsedTime(&ms, e0, e1));
+            const double per = ms / (2 * ((steps + 1) / 2));
+            if (fp)
+                std::fprintf(fp, "{\"tile_x\": %d, \"tile_y\": %d, \"persistent_wgs\": %d, "
+                                 "\"instances\": %d, \"nodes\": %lld, \"ms_per_step\": %.6f, "
+                                 "\"mlups\": %.1f}\n",
+                             L.tile_x, L.tile_y, L.persistent_wgs, b->n, nodes, per,
+                             nodes / (per * 1e-3) / 1e6);
+            if (per < best_ms) {
+                best_ms = per;
+                best_L = L;
+            }
+        }
+        if (st != CLBM_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (fp) std::fclose(fp);
+    b->launch = best_L;
+    clbm_status st2 = apply_shape(b);
+    if (st != CLBM_OK) return st;
+    if (best) *best = best_L;
+    return st2;
+}
+
+}  // extern "C"

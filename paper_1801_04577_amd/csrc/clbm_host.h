@@ -1,0 +1,44 @@
+// clbm_host.h -- host-side parameter derivation shared by the single-lattice and
+// batched entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+
+#include "../../include/clbm.h"
+#include "clbm_device.h"
+
+namespace clbm {
+
+#define CLBM_HIP(call)                                    \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) {                           \
+            set_last_hip_error(e_, #call, __FILE__, __LINE__); \
+            return CLBM_ERR_HIP;                          \
+        }                                                 \
+    } while (0)
+
+void set_last_hip_error(hipError_t e, const char* what, const char* file, int line);
+
+constexpr int kRowAlign = 64;    // stored row pitch, in elements
+constexpr size_t kAlign = 256;   // workspace region alignment, bytes
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Rates {
+    double s_nu, s_b, s_3, s_4, l0, l1, l2;
+};
+
+// Relaxation rates: Sec. 2.1 (nu), Eq. (8) defaults, Sec. 3 no-slip rule for s_3,
+// Sec. 2.2 (alpha, c_T^2 = 2/5), Sec. 3.1 rule for lambda_2.
+clbm_status derive_rates(const clbm_params* p, Rates* r);
+// Full validation of a parameter block (sizes, sides, finite values, rates).
+clbm_status validate(const clbm_params* p, Rates* r);
+// Kernel constant block for a validated parameter block.
+LatticeConst make_const(const clbm_params* p, const Rates& r);
+int row_pitch(int nx);
+
+}  // namespace clbm

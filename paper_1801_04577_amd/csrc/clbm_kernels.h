@@ -1,0 +1,216 @@
+// clbm_kernels.h -- fused pull-scheme time step and its helpers (gfx950).
+//
+// One thread updates one node per row it owns: it gathers the 14 populations
+// that stream into the node (Eq. 11, Eq. 21), substitutes the wall links
+// (half-way bounce-back for f, Sec. 3; general bounce-back for g, Eq. 26-28),
+// collides (clbm_device.h) and stores the 14 post-collision populations at its
+// own address in the other buffer. Populations are structure-of-arrays planes
+// [i][ny][pitch]; flow planes 0..8 then temperature planes 9..13.
+#pragma once
+
+#include "clbm_device.h"
+
+namespace clbm {
+
+// Gather the pre-collision deviations of node (x, y) at time t+1 from the
+// post-collision buffer at time t, with all wall substitutions applied.
+template <typename S>
+__device__ __forceinline__ void gather_node(const S* __restrict__ src, const LatticeConst& c, int x,
+                                            int y, float a[9], float b[5])
+{
+    const int nx = c.nx, ny = c.ny, pitch = c.pitch;
+    const unsigned P = c.plane;
+    // Source coordinates of the links; a link whose source lies outside a wall is
+    // flagged and its source clamped to the node itself (the address is never used).
+    int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
+    bool oxm = false, oxp = false, oym = false, oyp = false;
+    if (xm < 0) { if (c.periodic_x) xm = nx - 1; else { oxm = true; xm = x; } }
+    if (xp >= nx) { if (c.periodic_x) xp = 0; else { oxp = true; xp = x; } }
+    if (ym < 0) { if (c.periodic_y) ym = ny - 1; else { oym = true; ym = y; } }
+    if (yp >= ny) { if (c.periodic_y) yp = 0; else { oyp = true; yp = y; } }
+    const unsigned rC = (unsigned)y * pitch, rM = (unsigned)ym * pitch, rP = (unsigned)yp * pitch;
+    const unsigned own = rC + x;
+
+    // Eq. (11) pull form f_i(x, t+1) = f_i*(x - e_i, t); a wall link takes the
+    // opposite population of the node itself (half-way bounce-back).
+    a[0] = ld(src + own);
+    a[1] = ld(src + (oxm ? 3 * P + own : 1 * P + rC + xm));
+    a[2] = ld(src + (oym ? 4 * P + own : 2 * P + rM + x));
+    a[3] = ld(src + (oxp ? 1 * P + own : 3 * P + rC + xp));
+    a[4] = ld(src + (oyp ? 2 * P + own : 4 * P + rP + x));
+    a[5] = ld(src + ((oxm | oym) ? 7 * P + own : 5 * P + rM + xm));
+    a[6] = ld(src + ((oxp | oym) ? 8 * P + own : 6 * P + rM + xp));
+    a[7] = ld(src + ((oxp | oyp) ? 5 * P + own : 7 * P + rP + xp));
+    a[8] = ld(src + ((oxm | oyp) ? 6 * P + own : 8 * P + rP + xm));
+    // Eq. (21); a wall link loads the opposite population of the node, completed below.
+    const S* gs = src + 9 * P;
+    b[0] = ld(gs + own);
+    b[1] = ld(gs + (oxm ? 3 * P + own : 1 * P + rC + xm));
+    b[2] = ld(gs + (oym ? 4 * P + own : 2 * P + rM + x));
+    b[3] = ld(gs + (oxp ? 1 * P + own : 3 * P + rC + xp));
+    b[4] = ld(gs + (oyp ? 2 * P + own : 4 * P + rP + x));
+
+    if (oxm | oxp | oym | oyp) {
+        // Eq. (26): g_i(x_f, t+1) = -g*_opp(i)(x_f, t) + c_T^2 T_w, with T_w from Eq. (28)
+        // using T at this node (T1) and one node further from the wall (T2) at time t.
+        // Stored post-collision data give T = sum g* - Q/2 (the collision adds Q).
+        auto theta_at = [&](unsigned off) {
+            float s = ld(gs + off) + ld(gs + P + off) + ld(gs + 2 * P + off) + ld(gs + 3 * P + off)
+                      + ld(gs + 4 * P + off);
+            return s - 0.5f * c.Q;
+        };
+        const float th1 = theta_at(own);
+        if (oxm) {
+            const float tw = c.a1[0] * th1 + c.a2[0] * theta_at(rC + x + 1) + c.a3[0];
+            b[1] = -b[1] + CT2 * tw;
+        }
+        if (oxp) {
+            const float tw = c.a1[1] * th1 + c.a2[1] * theta_at(rC + x - 1) + c.a3[1];
+            b[3] = -b[3] + CT2 * tw;
+        }
+        if (oym) {
+            const float tw = c.a1[2] * th1 + c.a2[2] * theta_at(rC + pitch + x) + c.a3[2];
+            b[2] = -b[2] + CT2 * tw;
+        }
+        if (oyp) {
+            const float tw = c.a1[3] * th1 + c.a2[3] * theta_at(rC - pitch + x) + c.a3[3];
+            b[4] = -b[4] + CT2 * tw;
+        }
+        if (c.moving) {
+            // Tangentially moving wall: a bounced link j gains 2 w_j rho (e_j . u_w)/c_s^2,
+            // rho of the node at time t; u_w collects the speeds of the walls the link
+            // crosses (x component from a y wall, y component from an x wall). Links
+            // normal to a wall have e_j . u_w = 0.
+            float r = 1.f;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) r += ld(src + i * P + own);
+            const float k = 6.f * r * wgt(5);
+            const float u_bot = oym ? c.uw[2] : 0.f, u_top = oyp ? c.uw[3] : 0.f;   // along x
+            const float v_lft = oxm ? c.uw[0] : 0.f, v_rgt = oxp ? c.uw[1] : 0.f;   // along y
+            if (oxm | oym) a[5] += k * (u_bot + v_lft);
+            if (oxp | oym) a[6] += k * (-u_bot + v_rgt);
+            if (oxp | oyp) a[7] += k * (-u_top - v_rgt);
+            if (oxm | oyp) a[8] += k * (u_top - v_lft);
+        }
+    }
+}
+
+// Store the post-collision state of one node: flow deviations rounded to nearest,
+// temperature deviations (FP64 on entry) with the unbiased rounding of st_dither.
+template <typename S>
+__device__ __forceinline__ void store_node(S* __restrict__ dst, const LatticeConst& c, unsigned own,
+                                           const float a[9], const double tb[5])
+{
+    const unsigned P = c.plane;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) st(dst + i * P + own, a[i]);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) st_dither(dst + (9 + i) * P + own, tb[i]);
+}
+
+template <typename S>
+__device__ __forceinline__ void load_own(const S* __restrict__ src, const LatticeConst& c,
+                                         unsigned own, float a[9], float b[5])
+{
+    const unsigned P = c.plane;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) a[i] = ld(src + i * P + own);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) b[i] = ld(src + (9 + i) * P + own);
+}
+
+// Tile -> workgroup map. With xcd_remap the grid is padded to a multiple of 8 and
+// workgroup b (dispatched to XCD b % 8) takes tile (b % 8) * (grid/8) + b/8, so
+// each XCD sweeps one contiguous band of tiles.
+__device__ __forceinline__ int tile_of_block(int total, int remap)
+{
+    const int b = blockIdx.x;
+    if (!remap) return b;
+    const int per = gridDim.x >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+template <typename S, int ROWS>
+__global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __restrict__ dst,
+                                               const LatticeConst c, int tiles_x, int tiles_total,
+                                               int remap)
+{
+    const int t = tile_of_block(tiles_total, remap);
+    if (t >= tiles_total) return;
+    const int tx = t % tiles_x, ty = t / tiles_x;
+    const int x = tx * blockDim.x + threadIdx.x;
+    const int y0 = (ty * blockDim.y + threadIdx.y) * ROWS;
+    if (x >= c.nx) return;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int y = y0 + r;
+        if (y < c.ny) {
+            float a[9], b[5];
+            double tb[5];
+            gather_node(src, c, x, y, a, b);
+            NodeMacro m;
+            collide(c, a, b, tb, m);
+            store_node(dst, c, (unsigned)y * c.pitch + x, a, tb);
+        }
+    }
+}
+
+// Equilibrium at the given fields followed by one collision: the stored state is
+// the post-collision state at t = 0.
+template <typename S>
+__global__ void __launch_bounds__(256) k_init(S* __restrict__ dst, const LatticeConst c,
+                                              const float* __restrict__ rho,
+                                              const float* __restrict__ ux,
+                                              const float* __restrict__ uy,
+                                              const float* __restrict__ T)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= c.nx || y >= c.ny) return;
+    const size_t k = (size_t)y * c.nx + x;
+    const float drho = rho ? rho[k] - 1.f : 0.f;
+    const float vx = ux ? ux[k] : 0.f;
+    const float vy = uy ? uy[k] : 0.f;
+    const float th = T ? T[k] - c.T0 : 0.f;
+    float a[9], b[5];
+    double tb[5];
+    equilibrium(drho, vx, vy, th, c.T0, a, b);
+    NodeMacro m;
+    collide(c, a, b, tb, m);
+    store_node(dst, c, (unsigned)y * c.pitch + x, a, tb);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_macros(const S* __restrict__ src, const LatticeConst c,
+                                                float* __restrict__ rho, float* __restrict__ ux,
+                                                float* __restrict__ uy, float* __restrict__ T)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= c.nx || y >= c.ny) return;
+    float a[9], b[5];
+    load_own(src, c, (unsigned)y * c.pitch + x, a, b);
+    const NodeMacro m = macros_from_post(c, a, b);
+    const size_t k = (size_t)y * c.nx + x;
+    if (rho) rho[k] = 1.f + m.drho;
+    if (ux) ux[k] = m.ux;
+    if (uy) uy[k] = m.uy;
+    if (T) T[k] = c.T0 + m.theta;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_populations(const S* __restrict__ src, const LatticeConst c,
+                                                     float* __restrict__ f, float* __restrict__ g)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= c.nx || y >= c.ny) return;
+    const unsigned own = (unsigned)y * c.pitch + x;
+    const size_t n = (size_t)c.nx * c.ny, k = (size_t)y * c.nx + x;
+    if (f)
+        for (int i = 0; i < 9; ++i) f[i * n + k] = ld(src + (size_t)i * c.plane + own);
+    if (g)
+        for (int i = 0; i < 5; ++i) g[i * n + k] = ld(src + (size_t)(9 + i) * c.plane + own);
+}
+
+}  // namespace clbm

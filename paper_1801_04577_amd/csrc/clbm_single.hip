@@ -1,0 +1,659 @@
+// clbm_single.hip -- single-lattice entry points of the C ABI (include/clbm.h)
+// and the kernels they launch besides the fused step: initialisation,
+// macroscopic fields, population export and the diagnostics reductions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "clbm_host.h"
+#include "clbm_kernels.h"
+
+namespace clbm {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+
+static thread_local char g_last_error[512] = "";
+
+void set_last_hip_error(hipError_t e, const char* what, const char* file, int line)
+{
+    std::snprintf(g_last_error, sizeof g_last_error, "%s: %s (%s:%d)", hipGetErrorString(e), what,
+                  file, line);
+}
+
+// ---------------------------------------------------------------------------
+// Parameters
+// ---------------------------------------------------------------------------
+
+static bool in_open_02(double v) { return v > 0.0 && v < 2.0; }
+
+clbm_status derive_rates(const clbm_params* p, Rates* r)
+{
+    if (!p || !r) return CLBM_ERR_INVALID_ARG;
+    if (!(p->nu > 0.0) || !(p->alpha > 0.0) || !std::isfinite(p->nu) || !std::isfinite(p->alpha))
+        return CLBM_ERR_INVALID_ARG;
+    r->s_nu = 1.0 / (3.0 * p->nu + 0.5);
+    r->s_b = std::isnan(p->s_b) ? 1.0 : p->s_b;
+    r->s_4 = std::isnan(p->s_4) ? 1.0 : p->s_4;
+    r->s_3 = std::isnan(p->s_3) ? (16.0 - 8.0 * r->s_nu) / (8.0 - r->s_nu) : p->s_3;
+    r->l0 = std::isnan(p->lambda_0) ? 1.0 : p->lambda_0;
+    r->l1 = 1.0 / (p->alpha / 0.4 + 0.5);
+    r->l2 = std::isnan(p->lambda_2) ? 12.0 * (r->l1 - 2.0) / (r->l1 - 12.0) : p->lambda_2;
+    const double all[7] = {r->s_nu, r->s_b, r->s_3, r->s_4, r->l0, r->l1, r->l2};
+    for (double v : all)
+        if (!in_open_02(v)) return CLBM_ERR_UNSTABLE_PARAMS;
+    return CLBM_OK;
+}
+
+int row_pitch(int nx) { return (int)align_up((size_t)nx, kRowAlign); }
+
+clbm_status validate(const clbm_params* p, Rates* r)
+{
+    if (!p) return CLBM_ERR_INVALID_ARG;
+    if (p->nx < 1 || p->ny < 1) return CLBM_ERR_INVALID_ARG;
+    if (p->precision != CLBM_FP32 && p->precision != CLBM_FP16_SHIFTED) return CLBM_ERR_INVALID_ARG;
+    const double scal[] = {p->g_beta, p->T0, p->Fx, p->Fy, p->Q};
+    for (double v : scal)
+        if (!std::isfinite(v)) return CLBM_ERR_INVALID_ARG;
+    for (int s = 0; s < 4; ++s) {
+        const clbm_side& sd = p->side[s];
+        if (sd.kind != CLBM_PERIODIC && sd.kind != CLBM_WALL) return CLBM_ERR_INVALID_ARG;
+        if (sd.kind == CLBM_WALL) {
+            if (!std::isfinite(sd.u_wall) || !std::isfinite(sd.b1) || !std::isfinite(sd.b2) ||
+                !std::isfinite(sd.b3))
+                return CLBM_ERR_INVALID_ARG;
+            if (8.0 * sd.b1 + 3.0 * sd.b2 == 0.0) return CLBM_ERR_INVALID_ARG;  // Eq. (28) singular
+        }
+    }
+    if (p->side[0].kind != p->side[1].kind || p->side[2].kind != p->side[3].kind)
+        return CLBM_ERR_INVALID_ARG;
+    // Eq. (27) needs a second layer of nodes next to each wall.
+    if (p->side[0].kind == CLBM_WALL && p->nx < 2) return CLBM_ERR_INVALID_ARG;
+    if (p->side[2].kind == CLBM_WALL && p->ny < 2) return CLBM_ERR_INVALID_ARG;
+    // 32-bit element offsets inside one 14-plane buffer.
+    const double elems = 14.0 * (double)p->ny * (double)row_pitch(p->nx);
+    if (elems >= 4294967295.0) return CLBM_ERR_UNSUPPORTED;
+    Rates tmp;
+    clbm_status st = derive_rates(p, r ? r : &tmp);
+    return st;
+}
+
+LatticeConst make_const(const clbm_params* p, const Rates& r)
+{
+    LatticeConst c;
+    std::memset(&c, 0, sizeof c);
+    c.nx = p->nx;
+    c.ny = p->ny;
+    c.pitch = row_pitch(p->nx);
+    c.plane = (unsigned)((size_t)c.pitch * (size_t)p->ny);
+    c.periodic_x = p->side[0].kind == CLBM_PERIODIC;
+    c.periodic_y = p->side[2].kind == CLBM_PERIODIC;
+    const double sp = 0.5 * (r.s_b + r.s_nu), sm = 0.5 * (r.s_b - r.s_nu);
+    c.one_m_sp = (float)(1.0 - sp);
+    c.sm = (float)sm;
+    c.one_m_snu = (float)(1.0 - r.s_nu);
+    c.one_m_s3 = (float)(1.0 - r.s_3);
+    c.half_s3c = (float)((1.0 - 0.5 * r.s_3) / 3.0);
+    c.one_m_s4 = (float)(1.0 - r.s_4);
+    c.one_m_l1 = (float)(1.0 - r.l1);
+    c.one_m_l2 = (float)(1.0 - r.l2);
+    c.src2 = (float)((1.0 - 0.5 * r.l2) * 0.4 * p->Q);
+    c.g_beta = (float)p->g_beta;
+    c.Fx = (float)p->Fx;
+    c.Fy = (float)p->Fy;
+    c.Q = (float)p->Q;
+    c.T0 = (float)p->T0;
+    c.moving = 0;
+    for (int s = 0; s < 4; ++s) {
+        const clbm_side& sd = p->side[s];
+        if (sd.kind != CLBM_WALL) continue;
+        c.uw[s] = (float)sd.u_wall;
+        if (sd.u_wall != 0.0) c.moving = 1;
+        // Eq. (28) with n . e_i = 1, dx = 1, in theta = T - T0.
+        const double D = 8.0 * sd.b1 + 3.0 * sd.b2;
+        c.a1[s] = (float)(9.0 * sd.b1 / D);
+        c.a2[s] = (float)(-sd.b1 / D);
+        c.a3[s] = (float)(3.0 * (sd.b3 - sd.b2 * p->T0) / D);
+    }
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels besides the step
+// ---------------------------------------------------------------------------
+
+// Diagnostics. Per node: rho - 1, |u|^2, |u - u_snap|^2, T^2, (T - T_snap)^2, NaN flag;
+// per wall node: outward dT/dn (Eq. 27) and T_w (Eq. 28). Sums in FP64: wave64
+// shuffles, then LDS across the waves of the workgroup, then one partial per
+// workgroup; k_diag_final adds the partials in a fixed order.
+constexpr int kDiagSums = 15;  // drho, u2, du2, T2, dT2, dTdn[4], Tw[4], nan, count
+constexpr int kDiagBlock = 256;
+constexpr int kDiagMaxBlocks = 1024;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kDiagBlock) k_diag(const S* __restrict__ src, const LatticeConst c,
+                                                     float* __restrict__ snap, int have_snap,
+                                                     double* __restrict__ partial)
+{
+    double acc[kDiagSums];
+#pragma unroll
+    for (int k = 0; k < kDiagSums; ++k) acc[k] = 0.0;
+    const size_t n = (size_t)c.nx * c.ny;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const unsigned P = c.plane;
+    const S* gs = src + 9 * P;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const int y = (int)(k / c.nx), x = (int)(k - (size_t)y * c.nx);
+        const unsigned own = (unsigned)y * c.pitch + x;
+        float a[9], b[5];
+        load_own(src, c, own, a, b);
+        const NodeMacro m = macros_from_post(c, a, b);
+        const float T = c.T0 + m.theta;
+        const bool bad = !(isfinite(m.drho) && isfinite(m.ux) && isfinite(m.uy) && isfinite(T));
+        acc[0] += m.drho;
+        acc[1] += (double)m.ux * m.ux + (double)m.uy * m.uy;
+        acc[3] += (double)T * T;
+        if (have_snap) {
+            const double dx = m.ux - snap[k], dy = m.uy - snap[n + k], dt = T - snap[2 * n + k];
+            acc[2] += dx * dx + dy * dy;
+            acc[4] += dt * dt;
+        }
+        snap[k] = m.ux;
+        snap[n + k] = m.uy;
+        snap[2 * n + k] = T;
+        acc[13] += bad ? 1.0 : 0.0;
+        // Wall nodes: Eq. (27)-(28) with T1 at the node and T2 one node inward.
+        const bool wall[4] = {!c.periodic_x && x == 0, !c.periodic_x && x == c.nx - 1,
+                              !c.periodic_y && y == 0, !c.periodic_y && y == c.ny - 1};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (!wall[s]) continue;
+            const int x2 = s == 0 ? x + 1 : (s == 1 ? x - 1 : x);
+            const int y2 = s == 2 ? y + 1 : (s == 3 ? y - 1 : y);
+            const unsigned o2 = (unsigned)y2 * c.pitch + x2;
+            float sum2 = 0.f;
+            for (int i = 0; i < 5; ++i) sum2 += ld(gs + i * P + o2);
+            const float th2 = sum2 - 0.5f * c.Q;
+            const float thw = c.a1[s] * m.theta + c.a2[s] * th2 + c.a3[s];
+            acc[5 + s] += (8.0 * thw - 9.0 * m.theta + th2) / 3.0;
+            acc[9 + s] += (double)c.T0 + thw;
+        }
+        acc[14] += 1.0;
+    }
+    __shared__ double lds[kDiagBlock / 64][kDiagSums];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kDiagSums; ++k) {
+        const double v = wave_sum(acc[k]);
+        if (lane == 0) lds[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kDiagSums) {
+        double v = 0.0;
+        for (int w = 0; w < kDiagBlock / 64; ++w) v += lds[w][threadIdx.x];
+        partial[(size_t)blockIdx.x * kDiagSums + threadIdx.x] = v;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_diag_final(const double* __restrict__ partial, int nparts,
+                                                    double* __restrict__ out)
+{
+    __shared__ double lds[256];
+    for (int k = 0; k < kDiagSums; ++k) {
+        double v = 0.0;
+        for (int p = threadIdx.x; p < nparts; p += blockDim.x) v += partial[(size_t)p * kDiagSums + k];
+        lds[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = lds[0];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step launcher (shared with the graph builder)
+// ---------------------------------------------------------------------------
+
+struct StepLaunch {
+    const void* fn;
+    dim3 grid, block;
+    int tiles_x, tiles_total, remap;
+};
+
+template <typename S>
+static const void* step_fn(int rows)
+{
+    switch (rows) {
+        case 2: return reinterpret_cast<const void*>(&k_step<S, 2>);
+        case 4: return reinterpret_cast<const void*>(&k_step<S, 4>);
+        default: return reinterpret_cast<const void*>(&k_step<S, 1>);
+    }
+}
+
+static StepLaunch plan_step(const LatticeConst& c, int precision, const clbm_launch& L)
+{
+    StepLaunch s;
+    s.fn = precision == CLBM_FP16_SHIFTED ? step_fn<__half>(L.rows_per_thread)
+                                          : step_fn<float>(L.rows_per_thread);
+    s.block = dim3(L.block_x, L.block_y, 1);
+    s.tiles_x = (c.nx + L.block_x - 1) / L.block_x;
+    const int rows_per_tile = L.block_y * L.rows_per_thread;
+    const int tiles_y = (c.ny + rows_per_tile - 1) / rows_per_tile;
+    s.tiles_total = s.tiles_x * tiles_y;
+    s.remap = L.xcd_remap ? 1 : 0;
+    const int g = s.remap ? (int)align_up((size_t)s.tiles_total, 8) : s.tiles_total;
+    s.grid = dim3(g, 1, 1);
+    return s;
+}
+
+static bool launch_ok(const clbm_launch& L)
+{
+    const int threads = L.block_x * L.block_y;
+    if (L.block_x < 1 || L.block_y < 1 || threads % 64 != 0 || threads > 1024) return false;
+    return L.rows_per_thread == 1 || L.rows_per_thread == 2 || L.rows_per_thread == 4;
+}
+
+static clbm_launch default_launch()
+{
+    clbm_launch L;
+    L.block_x = 256;
+    L.block_y = 1;
+    L.rows_per_thread = 1;
+    L.xcd_remap = 0;
+    return L;
+}
+
+}  // namespace clbm
+
+using namespace clbm;
+
+// ---------------------------------------------------------------------------
+// Handle
+// ---------------------------------------------------------------------------
+
+struct clbm_handle {
+    clbm_params p;
+    Rates rates;
+    LatticeConst c;
+    hipStream_t stream;
+    int elem;            // bytes per stored population
+    size_t buf_bytes;    // bytes of one 14-plane buffer
+    void* buf[2];
+    float* snap;         // (u_x, u_y, T), 3 dense planes
+    double* partial;     // kDiagMaxBlocks x kDiagSums
+    double* result;      // kDiagSums
+    int cur;             // buffer holding the current post-collision state
+    long step;
+    long snap_step;      // -1: no snapshot
+    clbm_launch launch;
+    int graph_steps;
+    hipGraphExec_t gexec[2];  // graph_steps steps starting from buffer 0 / 1
+    hipGraph_t graph[2];
+};
+
+namespace {
+
+size_t layout(const clbm_params* p, size_t* buf_bytes, size_t* off_snap, size_t* off_part,
+              size_t* off_res)
+{
+    const size_t elem = p->precision == CLBM_FP16_SHIFTED ? 2 : 4;
+    const size_t plane = (size_t)row_pitch(p->nx) * (size_t)p->ny;
+    const size_t bb = align_up(14 * plane * elem, kAlign);
+    const size_t n = (size_t)p->nx * p->ny;
+    size_t off = 2 * bb;
+    const size_t snap = off;
+    off = align_up(off + 3 * n * sizeof(float), kAlign);
+    const size_t part = off;
+    off = align_up(off + (size_t)kDiagMaxBlocks * kDiagSums * sizeof(double), kAlign);
+    const size_t res = off;
+    off = align_up(off + kDiagSums * sizeof(double), kAlign);
+    if (buf_bytes) *buf_bytes = bb;
+    if (off_snap) *off_snap = snap;
+    if (off_part) *off_part = part;
+    if (off_res) *off_res = res;
+    return off;
+}
+
+void drop_graphs(clbm_handle* h)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (h->gexec[k]) (void)hipGraphExecDestroy(h->gexec[k]);
+        if (h->graph[k]) (void)hipGraphDestroy(h->graph[k]);
+        h->gexec[k] = nullptr;
+        h->graph[k] = nullptr;
+    }
+}
+
+clbm_status launch_steps_direct(clbm_handle* h, int n)
+{
+    const StepLaunch s = plan_step(h->c, h->p.precision, h->launch);
+    for (int k = 0; k < n; ++k) {
+        void* src = h->buf[h->cur];
+        void* dst = h->buf[h->cur ^ 1];
+        LatticeConst c = h->c;
+        int tx = s.tiles_x, tt = s.tiles_total, rm = s.remap;
+        void* args[] = {&src, &dst, &c, &tx, &tt, &rm};
+        CLBM_HIP(hipLaunchKernel(s.fn, s.grid, s.block, args, 0, h->stream));
+        h->cur ^= 1;
+        h->step++;
+    }
+    return CLBM_OK;
+}
+
+clbm_status build_graph(clbm_handle* h, int start)
+{
+    const StepLaunch s = plan_step(h->c, h->p.precision, h->launch);
+    hipGraph_t g = nullptr;
+    CLBM_HIP(hipGraphCreate(&g, 0));
+    hipGraphNode_t prev = nullptr;
+    int cur = start;
+    // Argument storage must outlive hipGraphAddKernelNode only (it copies the values).
+    for (int k = 0; k < h->graph_steps; ++k) {
+        void* src = h->buf[cur];
+        void* dst = h->buf[cur ^ 1];
+        LatticeConst c = h->c;
+        int tx = s.tiles_x, tt = s.tiles_total, rm = s.remap;
+        void* args[] = {&src, &dst, &c, &tx, &tt, &rm};
+        hipKernelNodeParams kp;
+        std::memset(&kp, 0, sizeof kp);
+        kp.func = const_cast<void*>(s.fn);
+        kp.gridDim = s.grid;
+        kp.blockDim = s.block;
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            set_last_hip_error(e, "hipGraphAddKernelNode", __FILE__, __LINE__);
+            return CLBM_ERR_HIP;
+        }
+        prev = node;
+        cur ^= 1;
+    }
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        set_last_hip_error(e, "hipGraphInstantiate", __FILE__, __LINE__);
+        return CLBM_ERR_HIP;
+    }
+    h->graph[start] = g;
+    h->gexec[start] = ex;
+    return CLBM_OK;
+}
+
+dim3 node_grid(const LatticeConst& c, dim3 blk)
+{
+    return dim3((c.nx + blk.x - 1) / blk.x, (c.ny + blk.y - 1) / blk.y, 1);
+}
+
+}  // namespace
+
+extern "C" {
+
+int clbm_abi_version(void) { return CLBM_ABI_VERSION; }
+
+const char* clbm_status_string(int status)
+{
+    switch (status) {
+        case CLBM_OK: return "ok";
+        case CLBM_ERR_INVALID_ARG: return "invalid argument";
+        case CLBM_ERR_UNSTABLE_PARAMS: return "relaxation rate outside (0, 2)";
+        case CLBM_ERR_BUFFER_TOO_SMALL: return "workspace too small";
+        case CLBM_ERR_HIP: return g_last_error[0] ? g_last_error : "HIP runtime error";
+        case CLBM_ERR_NAN: return "non-finite values in the state";
+        case CLBM_ERR_UNSUPPORTED: return "unsupported configuration";
+        default: return "unknown status";
+    }
+}
+
+clbm_status clbm_derive_rates(const clbm_params* p, double out[7])
+{
+    if (!p || !out) return CLBM_ERR_INVALID_ARG;
+    Rates r;
+    clbm_status st = derive_rates(p, &r);
+    out[0] = r.s_nu; out[1] = r.s_b; out[2] = r.s_3; out[3] = r.s_4;
+    out[4] = r.l0;   out[5] = r.l1;  out[6] = r.l2;
+    return st;
+}
+
+clbm_status clbm_workspace_bytes(const clbm_params* p, size_t* bytes)
+{
+    if (!p || !bytes) return CLBM_ERR_INVALID_ARG;
+    clbm_status st = validate(p, nullptr);
+    if (st != CLBM_OK) return st;
+    *bytes = layout(p, nullptr, nullptr, nullptr, nullptr);
+    return CLBM_OK;
+}
+
+clbm_status clbm_create(const clbm_params* p, void* d_workspace, size_t bytes, void* hip_stream,
+                        clbm_handle** out)
+{
+    if (!p || !out) return CLBM_ERR_INVALID_ARG;
+    *out = nullptr;
+    Rates r;
+    clbm_status st = validate(p, &r);
+    if (st != CLBM_OK) return st;
+    size_t bb, o_snap, o_part, o_res;
+    const size_t need = layout(p, &bb, &o_snap, &o_part, &o_res);
+    if (!d_workspace) return CLBM_ERR_INVALID_ARG;
+    if (((uintptr_t)d_workspace) % kAlign != 0) return CLBM_ERR_INVALID_ARG;
+    if (bytes < need) return CLBM_ERR_BUFFER_TOO_SMALL;
+    clbm_handle* h = new (std::nothrow) clbm_handle;
+    if (!h) return CLBM_ERR_INVALID_ARG;
+    std::memset(h, 0, sizeof *h);
+    h->p = *p;
+    h->rates = r;
+    h->c = make_const(p, r);
+    h->stream = (hipStream_t)hip_stream;
+    h->elem = p->precision == CLBM_FP16_SHIFTED ? 2 : 4;
+    h->buf_bytes = bb;
+    char* ws = (char*)d_workspace;
+    h->buf[0] = ws;
+    h->buf[1] = ws + bb;
+    h->snap = (float*)(ws + o_snap);
+    h->partial = (double*)(ws + o_part);
+    h->result = (double*)(ws + o_res);
+    h->launch = default_launch();
+    h->graph_steps = 0;
+    h->snap_step = -1;
+    st = clbm_init_from_fields(h, nullptr, nullptr, nullptr, nullptr);
+    if (st != CLBM_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return CLBM_OK;
+}
+
+void clbm_destroy(clbm_handle* h)
+{
+    if (!h) return;
+    drop_graphs(h);
+    delete h;
+}
+
+clbm_status clbm_init_from_fields(clbm_handle* h, const float* d_rho, const float* d_ux,
+                                  const float* d_uy, const float* d_T)
+{
+    if (!h) return CLBM_ERR_INVALID_ARG;
+    const dim3 blk(64, 4, 1);
+    const dim3 grd = node_grid(h->c, blk);
+    if (h->p.precision == CLBM_FP16_SHIFTED)
+        hipLaunchKernelGGL(k_init<__half>, grd, blk, 0, h->stream, (__half*)h->buf[0], h->c, d_rho,
+                           d_ux, d_uy, d_T);
+    else
+        hipLaunchKernelGGL(k_init<float>, grd, blk, 0, h->stream, (float*)h->buf[0], h->c, d_rho,
+                           d_ux, d_uy, d_T);
+    CLBM_HIP(hipGetLastError());
+    h->cur = 0;
+    h->step = 0;
+    h->snap_step = -1;
+    return CLBM_OK;
+}
+
+clbm_status clbm_step(clbm_handle* h, int nsteps)
+{
+    if (!h || nsteps < 0) return CLBM_ERR_INVALID_ARG;
+    int left = nsteps;
+    if (h->graph_steps > 0) {
+        while (left >= h->graph_steps) {
+            if (!h->gexec[h->cur]) {
+                clbm_status st = build_graph(h, h->cur);
+                if (st != CLBM_OK) return st;
+            }
+            CLBM_HIP(hipGraphLaunch(h->gexec[h->cur], h->stream));
+            // graph_steps is even: the state returns to the same buffer.
+            h->step += h->graph_steps;
+            left -= h->graph_steps;
+        }
+    }
+    return launch_steps_direct(h, left);
+}
+
+clbm_status clbm_macros(clbm_handle* h, float* d_rho, float* d_ux, float* d_uy, float* d_T)
+{
+    if (!h) return CLBM_ERR_INVALID_ARG;
+    const dim3 blk(64, 4, 1);
+    const dim3 grd = node_grid(h->c, blk);
+    if (h->p.precision == CLBM_FP16_SHIFTED)
+        hipLaunchKernelGGL(k_macros<__half>, grd, blk, 0, h->stream, (const __half*)h->buf[h->cur],
+                           h->c, d_rho, d_ux, d_uy, d_T);
+    else
+        hipLaunchKernelGGL(k_macros<float>, grd, blk, 0, h->stream, (const float*)h->buf[h->cur],
+                           h->c, d_rho, d_ux, d_uy, d_T);
+    CLBM_HIP(hipGetLastError());
+    return CLBM_OK;
+}
+
+clbm_status clbm_populations(clbm_handle* h, float* d_f, float* d_g)
+{
+    if (!h) return CLBM_ERR_INVALID_ARG;
+    const dim3 blk(64, 4, 1);
+    const dim3 grd = node_grid(h->c, blk);
+    if (h->p.precision == CLBM_FP16_SHIFTED)
+        hipLaunchKernelGGL(k_populations<__half>, grd, blk, 0, h->stream,
+                           (const __half*)h->buf[h->cur], h->c, d_f, d_g);
+    else
+        hipLaunchKernelGGL(k_populations<float>, grd, blk, 0, h->stream,
+                           (const float*)h->buf[h->cur], h->c, d_f, d_g);
+    CLBM_HIP(hipGetLastError());
+    return CLBM_OK;
+}
+
+clbm_status clbm_diagnostics(clbm_handle* h, clbm_diag* out)
+{
+    if (!h || !out) return CLBM_ERR_INVALID_ARG;
+    const size_t n = (size_t)h->p.nx * h->p.ny;
+    const int blocks = (int)std::min<size_t>((n + kDiagBlock - 1) / kDiagBlock, kDiagMaxBlocks);
+    const int have = h->snap_step >= 0 ? 1 : 0;
+    if (h->p.precision == CLBM_FP16_SHIFTED)
+        hipLaunchKernelGGL(k_diag<__half>, dim3(blocks), dim3(kDiagBlock), 0, h->stream,
+                           (const __half*)h->buf[h->cur], h->c, h->snap, have, h->partial);
+    else
+        hipLaunchKernelGGL(k_diag<float>, dim3(blocks), dim3(kDiagBlock), 0, h->stream,
+                           (const float*)h->buf[h->cur], h->c, h->snap, have, h->partial);
+    CLBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, h->stream, h->partial, blocks, h->result);
+    CLBM_HIP(hipGetLastError());
+    double r[kDiagSums];
+    CLBM_HIP(hipMemcpyAsync(r, h->result, sizeof r, hipMemcpyDeviceToHost, h->stream));
+    CLBM_HIP(hipStreamSynchronize(h->stream));
+    std::memset(out, 0, sizeof *out);
+    out->step = h->step;
+    out->K = have ? (int)(h->step - h->snap_step) : 0;
+    out->mass = (double)n + r[0];
+    out->sum_u2 = r[1];
+    out->sum_du2 = r[2];
+    out->sum_T2 = r[3];
+    out->sum_dT2 = r[4];
+    if (out->K > 0) {
+        out->res_u = r[1] > 0.0 ? std::sqrt(r[2] / r[1]) / out->K : 0.0;
+        out->res_T = r[3] > 0.0 ? std::sqrt(r[4] / r[3]) / out->K : 0.0;
+    }
+    const int len[4] = {h->p.ny, h->p.ny, h->p.nx, h->p.nx};
+    for (int s = 0; s < 4; ++s) {
+        if (h->p.side[s].kind != CLBM_WALL) continue;
+        out->dTdn[s] = r[5 + s] / len[s];
+        out->T_wall[s] = r[9 + s] / len[s];
+    }
+    out->nan_count = (long)r[13];
+    h->snap_step = h->step;
+    return out->nan_count > 0 ? CLBM_ERR_NAN : CLBM_OK;
+}
+
+clbm_status clbm_state_bytes(const clbm_handle* h, size_t* bytes)
+{
+    if (!h || !bytes) return CLBM_ERR_INVALID_ARG;
+    *bytes = h->buf_bytes;
+    return CLBM_OK;
+}
+
+clbm_status clbm_save(clbm_handle* h, void* d_dst)
+{
+    if (!h || !d_dst) return CLBM_ERR_INVALID_ARG;
+    CLBM_HIP(hipMemcpyAsync(d_dst, h->buf[h->cur], h->buf_bytes, hipMemcpyDeviceToDevice, h->stream));
+    return CLBM_OK;
+}
+
+clbm_status clbm_load(clbm_handle* h, const void* d_src, long step)
+{
+    if (!h || !d_src || step < 0) return CLBM_ERR_INVALID_ARG;
+    CLBM_HIP(hipMemcpyAsync(h->buf[h->cur], d_src, h->buf_bytes, hipMemcpyDeviceToDevice, h->stream));
+    h->step = step;
+    h->snap_step = -1;
+    return CLBM_OK;
+}
+
+clbm_status clbm_get_step(const clbm_handle* h, long* step)
+{
+    if (!h || !step) return CLBM_ERR_INVALID_ARG;
+    *step = h->step;
+    return CLBM_OK;
+}
+
+clbm_status clbm_set_launch(clbm_handle* h, const clbm_launch* launch)
+{
+    if (!h || !launch) return CLBM_ERR_INVALID_ARG;
+    clbm_launch L = *launch;
+    if (L.block_x == 0 && L.block_y == 0 && L.rows_per_thread == 0) L = default_launch();
+    if (!launch_ok(L)) return CLBM_ERR_INVALID_ARG;
+    h->launch = L;
+    drop_graphs(h);
+    return CLBM_OK;
+}
+
+clbm_status clbm_get_launch(const clbm_handle* h, clbm_launch* launch)
+{
+    if (!h || !launch) return CLBM_ERR_INVALID_ARG;
+    *launch = h->launch;
+    return CLBM_OK;
+}
+
+clbm_status clbm_set_graph(clbm_handle* h, int steps_per_graph)
+{
+    if (!h || steps_per_graph < 0 || (steps_per_graph % 2) != 0) return CLBM_ERR_INVALID_ARG;
+    drop_graphs(h);
+    h->graph_steps = steps_per_graph;
+    return CLBM_OK;
+}
+
+}  // extern "C"

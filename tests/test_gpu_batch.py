@@ -1,0 +1,136 @@
+"""Batched form: many lattices of uneven size and parameters advanced by one kernel
+launch per step over a device tile list, with on-device convergence checks and
+retirement (C ABI clbm_batch_*). Each instance must evolve exactly as the same lattice
+advanced alone (same per-node arithmetic), and the oracle bar applies to both."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from parity import f32, field_errors, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    import torch
+    import paper_1801_04577_amd as clbm
+    assert torch.cuda.is_available()
+    clbm.ensure_built()
+
+
+def mixed_problems():
+    probs = [W.cavity(64, 96, Ra=1e4, Pr=0.71),
+             W.cavity(130, 67, Ra=1e5, Pr=2.0, Q=5e-5),
+             W.channel(nx=70, ny=33),
+             W.cavity(33, 33, Ra=3e3, Pr=6.0),
+             W.couette(nx=65, ny=20, U=0.02, Q=1e-4),
+             W.cavity(200, 120, Ra=1e6, Pr=0.7, Q=1e-5)]
+    fields = []
+    for k, p in enumerate(probs):
+        fields.append({"T": f32(p["T0"] + W.noise_field(k + 1, p["nx"], p["ny"], 1e-4))})
+    return probs, fields
+
+
+def run_single(prob, fields, steps):
+    import torch
+    import paper_1801_04577_amd as clbm
+    s = clbm.Solver(prob)
+    s.init(**{k: torch.from_numpy(v) for k, v in fields.items()})
+    s.step(steps)
+    return s
+
+
+@pytest.mark.parametrize("launch", [None, dict(tile_x=128, tile_y=2, persistent_wgs=0),
+                                    dict(tile_x=64, tile_y=8, persistent_wgs=64)])
+def test_batch_equals_single_lattices(launch):
+    import torch
+    import paper_1801_04577_amd as clbm
+    probs, fields = mixed_problems()
+    b = clbm.Batch(probs, launch=launch)
+    for i, f in enumerate(fields):
+        b.init(i, **{k: torch.from_numpy(v) for k, v in f.items()})
+    b.step(150)
+    for i, (p, f) in enumerate(zip(probs, fields)):
+        s = run_single(p, f, 150)
+        for x, y in zip(b.macros(i), s.macros()):
+            assert torch.equal(x, y), (i, launch)
+
+
+def test_batch_instance_matches_oracle():
+    import torch
+    import paper_1801_04577_amd as clbm
+    probs, fields = mixed_problems()
+    b = clbm.Batch(probs)
+    for i, f in enumerate(fields):
+        b.init(i, **{k: torch.from_numpy(v) for k, v in f.items()})
+    b.step(300)
+    for i in (1, 4):
+        o = run_oracle(probs[i], 300, fields[i])
+
+        class View:  # field_errors reads .macros()
+            def macros(self_inner):
+                return b.macros(i)
+        e = field_errors(o, View())
+        assert e["u"] <= 1e-5 and e["T"] <= 1e-5, (i, e)
+
+
+def test_batch_run_converges_and_retires():
+    """Small cavities converge at different times; each retired instance stays frozen
+    while the others continue, and reports the step of its last window."""
+    import torch
+    import paper_1801_04577_amd as clbm
+    probs = [W.cavity(24, 24, Ra=1e3, Pr=0.71), W.cavity(32, 24, Ra=1e4, Pr=0.71),
+             W.cavity(40, 40, Ra=2e4, Pr=1.0)]
+    b = clbm.Batch(probs)
+    for i, p in enumerate(probs):
+        b.init(i, T=torch.from_numpy(f32(p["T0"] + W.noise_field(i, p["nx"], p["ny"], 1e-4))))
+    steps, status = b.run(max_steps=400000, tol=1e-6, K=200)
+    assert status == ["converged"] * 3, (steps, status)
+    assert all(s % 200 == 0 and s > 0 for s in steps)
+    assert len(set(steps)) > 1
+    for i in range(3):
+        ru, rT = b.residual(i)
+        assert max(ru, rT) < 1e-6
+    # frozen after retirement: a second run with tol=inf retires everything after one window
+    s2, st2 = b.run(max_steps=1000, tol=float("inf"), K=200)
+    assert st2 == ["converged"] * 3 and s2 == [200] * 3
+
+
+def test_batch_divergence_and_max_steps():
+    import torch
+    import paper_1801_04577_amd as clbm
+    probs = [W.cavity(32, 32, Ra=1e4), W.cavity(48, 40, Ra=1e5)]
+    b = clbm.Batch(probs)
+    T = f32(np.zeros((32, 32)))
+    T[5, 7] = np.nan
+    b.init(0, T=torch.from_numpy(T))
+    b.init(1)
+    steps, status = b.run(max_steps=600, tol=0.0, K=200)
+    assert status == ["diverged", "max_steps"], status
+    assert steps == [200, 600]
+
+
+def test_autotune_writes_cache_and_keeps_results(tmp_path):
+    import torch
+    import paper_1801_04577_amd as clbm
+    probs, fields = mixed_problems()
+    cache = str(tmp_path / "tune.jsonl")
+    b = clbm.Batch(probs)
+    best = b.autotune(steps=4, cache_path=cache)
+    lines = [json.loads(l) for l in open(cache)]
+    assert len(lines) >= 10 and all(l["ms_per_step"] > 0 for l in lines)
+    assert best["tile_x"] % 64 == 0
+    for i, f in enumerate(fields):
+        b.init(i, **{k: torch.from_numpy(v) for k, v in f.items()})
+    b.step(40)
+    ref = clbm.Batch(probs)
+    for i, f in enumerate(fields):
+        ref.init(i, **{k: torch.from_numpy(v) for k, v in f.items()})
+    ref.step(40)
+    for i in range(len(probs)):
+        for x, y in zip(b.macros(i), ref.macros(i)):
+            assert torch.equal(x, y)
