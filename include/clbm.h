@@ -172,6 +172,13 @@ clbm_status clbm_get_launch(const clbm_handle* h, clbm_launch* launch);
  * graphs of that many steps (the default is 0). */
 clbm_status clbm_set_graph(clbm_handle* h, int steps_per_graph);
 
+/* Plain device-to-device copy of `bytes` bytes (16-byte vector loads and stores,
+ * grid-stride; both pointers 16-byte aligned, bytes a multiple of 16) on the given
+ * stream. It is the bandwidth reference of the benchmark (a kernel whose HBM traffic
+ * is known exactly) and calibrates hardware traffic counters against the step kernel.
+ * Not part of the method. Asynchronous. */
+clbm_status clbm_stream_copy(void* d_dst, const void* d_src, size_t bytes, void* hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* Batched form: many independent lattices (each with its own size and        */
 /* parameters) advanced together, one kernel launch per time step over a      */

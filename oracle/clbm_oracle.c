@@ -220,14 +220,13 @@ int oracle_rates(const oracle_params* p, double out[7])
 /* Equilibria and the collision of one node                                  */
 /* ------------------------------------------------------------------------ */
 
-void oracle_equilibrium(double rho, double ux, double uy, double T, double f[9], double g[5])
+/* Eq. (9) and Eq. (19) mapped back to populations: f = M^-1 N^-1 Gamma~eq. */
+static void equilibrium_with(const double* Minv, const double* MTinv, double rho, double ux,
+                             double uy, double T, double f[9], double g[5])
 {
-    double Minv[81], MTinv[25], N[81], NT[25];
-    oracle_matrix_Minv(Minv);
-    oracle_matrix_MTinv(MTinv);
+    double N[81], NT[25];
     oracle_matrix_N(ux, uy, N);
     oracle_matrix_NT(ux, uy, NT);
-    /* Eq. (9) and Eq. (19). */
     double keq[Q9] = {rho, 0, 0, rho * CS2, rho * CS2, 0, 0, 0, rho * CS2 * CS2};
     double kteq[Q5] = {T, 0, 0, T * CT2, T * CT2};
     double raw[Q9], rawt[Q5];
@@ -235,6 +234,14 @@ void oracle_equilibrium(double rho, double ux, double uy, double T, double f[9],
     matvec(Q9, Minv, raw, f);
     solve_lower(Q5, NT, kteq, rawt);
     matvec(Q5, MTinv, rawt, g);
+}
+
+void oracle_equilibrium(double rho, double ux, double uy, double T, double f[9], double g[5])
+{
+    double Minv[81], MTinv[25];
+    oracle_matrix_Minv(Minv);
+    oracle_matrix_MTinv(MTinv);
+    equilibrium_with(Minv, MTinv, rho, ux, uy, T, f, g);
 }
 
 typedef struct {
@@ -430,13 +437,16 @@ void oracle_destroy(oracle_sim* s)
 int oracle_init(oracle_sim* s, const double* rho, const double* ux, const double* uy,
                 const double* T)
 {
-    size_t n = (size_t)s->p.nx * (size_t)s->p.ny;
-    for (size_t k = 0; k < n; ++k) {
+    const long n = (long)s->p.nx * (long)s->p.ny;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (long k = 0; k < n; ++k) {
         double r = rho ? rho[k] : 1.0;
         double vx = ux ? ux[k] : 0.0;
         double vy = uy ? uy[k] : 0.0;
         double t = T ? T[k] : s->p.T0;
-        oracle_equilibrium(r, vx, vy, t, s->f + k * Q9, s->g + k * Q5);
+        equilibrium_with(s->c.Minv, s->c.MTinv, r, vx, vy, t, s->f + k * Q9, s->g + k * Q5);
     }
     s->step = 0;
     return ORACLE_OK;

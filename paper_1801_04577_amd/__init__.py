@@ -98,6 +98,7 @@ def _declare(L):
         "clbm_set_launch": (st, [_VP, ctypes.POINTER(clbm_launch)]),
         "clbm_get_launch": (st, [_VP, ctypes.POINTER(clbm_launch)]),
         "clbm_set_graph": (st, [_VP, ctypes.c_int]),
+        "clbm_stream_copy": (st, [_VP, _VP, ctypes.c_size_t, _VP]),
         "clbm_batch_workspace_bytes": (st, [ctypes.c_int, P, ctypes.POINTER(ctypes.c_size_t)]),
         "clbm_batch_create": (st, [ctypes.c_int, P, _VP, ctypes.c_size_t, _VP,
                                    ctypes.POINTER(clbm_batch_launch), ctypes.POINTER(_VP)]),
@@ -211,6 +212,15 @@ def clbm_batch_workspace_bytes(params_list):
     _check(lib().clbm_batch_workspace_bytes(len(params_list), arr, ctypes.byref(n)),
            "clbm_batch_workspace_bytes")
     return n.value
+
+
+def clbm_stream_copy(dst, src, stream=None):
+    """Device copy of src into dst (uint8/float tensors of equal byte size) by the
+    library's streaming-copy kernel (bandwidth reference)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    _check(lib().clbm_stream_copy(_addr(dst), _addr(src), nbytes, _stream_ptr(stream)),
+           "clbm_stream_copy")
 
 
 def _workspace(nbytes, device):

@@ -43,13 +43,10 @@ struct LatticeConst {
     float a1[4], a2[4], a3[4]; // theta_w = a1 theta_1 + a2 theta_2 + a3  (Eq. 28 in theta = T - T0)
 };
 
-// Storage conversion: float32 or binary16 (round to nearest even).
+// Storage loads: float32 or binary16.
 template <typename S> __device__ __forceinline__ float ld(const S* p);
 template <> __device__ __forceinline__ float ld<float>(const float* p) { return *p; }
 template <> __device__ __forceinline__ float ld<__half>(const __half* p) { return __half2float(*p); }
-template <typename S> __device__ __forceinline__ void st(S* p, float v);
-template <> __device__ __forceinline__ void st<float>(float* p, float v) { __builtin_nontemporal_store(v, p); }
-template <> __device__ __forceinline__ void st<__half>(__half* p, float v) { *p = __float2half_rn(v); }
 
 // Unbiased rounding into storage. x lies between the nearest storable value f and its
 // neighbour g on the other side of x; g is taken with probability |x - f|/|g - f|, the
@@ -73,6 +70,32 @@ __device__ __forceinline__ double dither_uniform(double x)
     return (double)(h >> 8) * (1.0 / 16777216.0);
 }
 
+// binary16 neighbour of h (value hf) on the side of r, and the dithered choice for a
+// value hf + r.
+__device__ __forceinline__ __half half_dither(__half h, float hf, float r, double u)
+{
+    const unsigned short fb = __half_as_ushort(h);
+    const bool up = r > 0.f;
+    const unsigned short gb = (unsigned short)((fb & 0x7fffu) == 0u
+        ? (up ? 0x0001u : 0x8001u)
+        : ((((fb >> 15) == 0u) == up) ? fb + 1u : fb - 1u));
+    const __half g = __ushort_as_half(gb);
+    const float gap = __half2float(g) - hf;
+    return fabsf((float)u * gap) < fabsf(r) ? g : h;
+}
+
+// Flow populations are computed in FP32: stored as is in FP32, and with the dithered
+// rounding (hash of the FP32 bits) in binary16, whose rounding error dominates.
+template <typename S> __device__ __forceinline__ void st(S* p, float v);
+template <> __device__ __forceinline__ void st<float>(float* p, float v) { __builtin_nontemporal_store(v, p); }
+template <> __device__ __forceinline__ void st<__half>(__half* p, float v)
+{
+    const __half h = __float2half_rn(v);
+    const float hf = __half2float(h);
+    const unsigned hb = mix32(__float_as_uint(v) ^ 0x9e3779b9u);
+    *p = half_dither(h, hf, v - hf, (double)(hb >> 8) * (1.0 / 16777216.0));
+}
+
 template <typename S> __device__ __forceinline__ void st_dither(S* p, double x);
 template <> __device__ __forceinline__ void st_dither<float>(float* p, double x)
 {
@@ -91,17 +114,9 @@ template <> __device__ __forceinline__ void st_dither<float>(float* p, double x)
 template <> __device__ __forceinline__ void st_dither<__half>(__half* p, double x)
 {
     const float xf = (float)x;
-    const __half f = __float2half_rn(xf);
-    const float ff = __half2float(f);
-    const float r = xf - ff;
-    const unsigned short fb = __half_as_ushort(f);
-    const bool up = r > 0.f;
-    const unsigned short gb = (unsigned short)((fb & 0x7fffu) == 0u
-        ? (up ? 0x0001u : 0x8001u)
-        : ((((fb >> 15) == 0u) == up) ? fb + 1u : fb - 1u));
-    const __half g = __ushort_as_half(gb);
-    const float gap = __half2float(g) - ff;
-    *p = fabsf((float)dither_uniform(x) * gap) < fabsf(r) ? g : f;
+    const __half h = __float2half_rn(xf);
+    const float hf = __half2float(h);
+    *p = half_dither(h, hf, xf - hf, dither_uniform(x));
 }
 
 struct NodeMacro {

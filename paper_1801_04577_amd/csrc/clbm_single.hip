@@ -226,6 +226,15 @@ __global__ void __launch_bounds__(256) k_diag_final(const double* __restrict__ p
     }
 }
 
+// Streaming copy used as the bandwidth reference (see clbm_stream_copy).
+__global__ void __launch_bounds__(256) k_stream_copy(float4* __restrict__ dst,
+                                                     const float4* __restrict__ src, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+        dst[k] = src[k];
+}
+
 // ---------------------------------------------------------------------------
 // Step launcher (shared with the graph builder)
 // ---------------------------------------------------------------------------
@@ -598,6 +607,19 @@ clbm_status clbm_diagnostics(clbm_handle* h, clbm_diag* out)
     out->nan_count = (long)r[13];
     h->snap_step = h->step;
     return out->nan_count > 0 ? CLBM_ERR_NAN : CLBM_OK;
+}
+
+clbm_status clbm_stream_copy(void* d_dst, const void* d_src, size_t bytes, void* hip_stream)
+{
+    if (!d_dst || !d_src || bytes % 16 != 0 || ((uintptr_t)d_dst | (uintptr_t)d_src) % 16 != 0)
+        return CLBM_ERR_INVALID_ARG;
+    const size_t n = bytes / 16;
+    if (n == 0) return CLBM_OK;
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, (hipStream_t)hip_stream,
+                       (float4*)d_dst, (const float4*)d_src, n);
+    CLBM_HIP(hipGetLastError());
+    return CLBM_OK;
 }
 
 clbm_status clbm_state_bytes(const clbm_handle* h, size_t* bytes)
