@@ -220,6 +220,10 @@ clbm_status clbm_batch_run(clbm_batch* b, long max_steps, double tol, int K, lon
                            int* status_out);
 clbm_status clbm_batch_macros(clbm_batch* b, int i, float* d_rho, float* d_ux, float* d_uy,
                               float* d_T);
+/* Diagnostics of instance i at its current state (mass, wall gradients and temperatures,
+ * field sums, NaN count; the residual fields are zero). Overwrites the instance's residual
+ * snapshot. Synchronises; step is the number of steps the last clbm_batch_run gave it. */
+clbm_status clbm_batch_diagnostics(clbm_batch* b, int i, clbm_diag* out);
 /* Host copy of instance i's last residuals {res_u, res_T}; synchronises. */
 clbm_status clbm_batch_residual(clbm_batch* b, int i, double out[2]);
 /* Times candidate tile shapes on the batch's own instances (each for `steps` steps
@@ -229,6 +233,82 @@ clbm_status clbm_batch_residual(clbm_batch* b, int i, double out[2]);
 clbm_status clbm_batch_autotune(clbm_batch* b, int steps, const char* cache_path,
                                 clbm_batch_launch* best);
 clbm_status clbm_batch_set_launch(clbm_batch* b, const clbm_batch_launch* launch);
+
+/* ------------------------------------------------------------------------ */
+/* Warm-start network: a four-level convolutional encoder-decoder with skip    */
+/* connections mapping input planes that describe a cavity problem to the       */
+/* steady fields (u_x, u_y, T) on a fixed grid. 3x3 convolutions run on BF16    */
+/* MFMA with FP32 accumulation; activations and their gradients are BF16,       */
+/* master weights, weight gradients and the Adam state FP32. Layer order and    */
+/* the canonical parameter layout: per convolution (15 of them, encoder levels  */
+/* cin->w1->w1, w1->w2->w2, w2->w3->w3, w3->w4->w4; decoder (w4+w3)->w3->w3,    */
+/* (w3+w2)->w2->w2, (w2+w1)->w1->w1; output w1->cout) W[cout][cin][3][3] then   */
+/* b[cout], float32. Every convolution but the last is followed by ReLU;        */
+/* downsampling is 2x2 averaging, upsampling is nearest-neighbour, the skip     */
+/* tensor is concatenated after the upsampled one.                              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int batch;          /* samples per forward/backward call */
+    int height, width;  /* grid, multiples of 8; batch*(height/8)*(width/8) a multiple of 64 */
+    int cin;            /* input planes, 1..32 */
+    int cout;           /* output fields, 1..16 */
+    int widths[4];      /* channels per level, multiples of 32 */
+} clbm_net_desc;
+
+typedef struct clbm_net clbm_net;
+
+/* Host only: number of floats in the canonical parameter vector / workspace bytes. */
+clbm_status clbm_net_param_count(const clbm_net_desc* d, size_t* count);
+clbm_status clbm_net_workspace_bytes(const clbm_net_desc* d, size_t* bytes);
+/* Creates the network over the caller's workspace (256-byte aligned) and zeroes it
+ * (parameters, Adam state). */
+clbm_status clbm_net_create(const clbm_net_desc* d, void* d_workspace, size_t bytes, void* hip_stream,
+                            clbm_net** out);
+void clbm_net_destroy(clbm_net* n);
+/* Device copies of the canonical parameter vector (and of the last gradients). */
+clbm_status clbm_net_set_params(clbm_net* n, const float* d_params);
+clbm_status clbm_net_get_params(clbm_net* n, float* d_params);
+clbm_status clbm_net_get_grads(clbm_net* n, float* d_grads);
+/* Forward pass: d_x [batch][cin][H][W] -> d_y [batch][cout][H][W] (float32 NCHW;
+ * d_y may be NULL). Keeps the activations for clbm_net_backward. Asynchronous. */
+clbm_status clbm_net_forward(clbm_net* n, const float* d_x, float* d_y);
+/* Backward pass of the mean squared error between the last forward output and d_target
+ * ([batch][cout][H][W]): fills the gradients of every parameter. *loss (host, may be
+ * NULL) receives the loss; a non-NULL loss synchronises the stream. */
+clbm_status clbm_net_backward(clbm_net* n, const float* d_target, double* loss);
+/* One Adam update of the parameters with the last gradients (step t >= 1). */
+clbm_status clbm_net_adam(clbm_net* n, float lr, float beta1, float beta2, float eps, int t);
+/* Bilinear resampling of nfields (<= 16) float32 fields [nfields][sh][sw] to
+ * [nfields][dh][dw] on cell-centred grids (edge values held), each output field
+ * multiplied by scale[f] and shifted by shift[f] (host arrays of nfields; NULL: 1 and 0).
+ * Moves fields between a lattice and the network grid. Asynchronous. */
+clbm_status clbm_resample_bilinear(const float* d_src, int sh, int sw, float* d_dst, int dh, int dw,
+                                   int nfields, const float* scale, const float* shift,
+                                   void* hip_stream);
+
+/* Scalar description of a cavity problem for the warm-start network (host struct).
+ * Dimensionless groups of Sec. 3.3: Ra = g beta dT H^3/(nu alpha), Pr = nu/alpha, and the
+ * source q_star = Q H^2/(alpha dT), with H = ny and dT the difference of the Dirichlet side-wall
+ * temperatures (1 if the side walls are not both Dirichlet). kind per side: 0 periodic,
+ * 1 Dirichlet, 2 adiabatic, 3 other Robin; theta_wall = (T_w - T0)/dT on Dirichlet sides.
+ * u_scale = sqrt(g beta dT H) and t_scale = dT are the units of the network's outputs. */
+typedef struct {
+    float log10_ra, pr, q_star, log2_aspect;
+    float theta_wall[4];
+    int kind[4];
+    float u_scale, t_scale;
+} clbm_problem_code;
+
+/* Host only: the code of a parameter block. */
+clbm_status clbm_problem_encode(const clbm_params* p, clbm_problem_code* out);
+
+/* Input planes of the network, [batch][8][height][width] float32, from one device
+ * clbm_problem_code per sample: 0 (log10 Ra - 4.5)/1.5, 1 (Pr - 3.85)/3.15, 2 q_star/4,
+ * 3 theta_wall on Dirichlet boundary cells, 4 Dirichlet mask, 5 adiabatic mask,
+ * 6 x in (-1, 1), 7 log2(nx/ny). Asynchronous. */
+clbm_status clbm_net_features(const clbm_problem_code* d_codes, int batch, int height, int width,
+                              float* d_out, void* hip_stream);
 
 #ifdef __cplusplus
 }

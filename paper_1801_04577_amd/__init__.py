@@ -67,6 +67,17 @@ class clbm_diag(ctypes.Structure):
                 "T_wall": list(self.T_wall), "nan_count": self.nan_count}
 
 
+class clbm_net_desc(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int), ("height", ctypes.c_int), ("width", ctypes.c_int),
+                ("cin", ctypes.c_int), ("cout", ctypes.c_int), ("widths", ctypes.c_int * 4)]
+
+
+class clbm_problem_code(ctypes.Structure):
+    _fields_ = [("log10_ra", ctypes.c_float), ("pr", ctypes.c_float), ("q_star", ctypes.c_float),
+                ("log2_aspect", ctypes.c_float), ("theta_wall", ctypes.c_float * 4),
+                ("kind", ctypes.c_int * 4), ("u_scale", ctypes.c_float), ("t_scale", ctypes.c_float)]
+
+
 class clbm_batch_launch(ctypes.Structure):
     _fields_ = [("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int), ("persistent_wgs", ctypes.c_int)]
 
@@ -99,6 +110,23 @@ def _declare(L):
         "clbm_get_launch": (st, [_VP, ctypes.POINTER(clbm_launch)]),
         "clbm_set_graph": (st, [_VP, ctypes.c_int]),
         "clbm_stream_copy": (st, [_VP, _VP, ctypes.c_size_t, _VP]),
+        "clbm_net_param_count": (st, [ctypes.POINTER(clbm_net_desc), ctypes.POINTER(ctypes.c_size_t)]),
+        "clbm_net_workspace_bytes": (st, [ctypes.POINTER(clbm_net_desc), ctypes.POINTER(ctypes.c_size_t)]),
+        "clbm_net_create": (st, [ctypes.POINTER(clbm_net_desc), _VP, ctypes.c_size_t, _VP,
+                                 ctypes.POINTER(_VP)]),
+        "clbm_net_destroy": (None, [_VP]),
+        "clbm_net_set_params": (st, [_VP, _VP]),
+        "clbm_net_get_params": (st, [_VP, _VP]),
+        "clbm_net_get_grads": (st, [_VP, _VP]),
+        "clbm_net_forward": (st, [_VP, _VP, _VP]),
+        "clbm_net_backward": (st, [_VP, _VP, ctypes.POINTER(ctypes.c_double)]),
+        "clbm_net_adam": (st, [_VP, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_int]),
+        "clbm_resample_bilinear": (st, [_VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
+                                        ctypes.POINTER(ctypes.c_float), _VP]),
+        "clbm_problem_encode": (st, [ctypes.POINTER(clbm_params), ctypes.POINTER(clbm_problem_code)]),
+        "clbm_net_features": (st, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, _VP]),
         "clbm_batch_workspace_bytes": (st, [ctypes.c_int, P, ctypes.POINTER(ctypes.c_size_t)]),
         "clbm_batch_create": (st, [ctypes.c_int, P, _VP, ctypes.c_size_t, _VP,
                                    ctypes.POINTER(clbm_batch_launch), ctypes.POINTER(_VP)]),
@@ -109,6 +137,7 @@ def _declare(L):
                                 ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_int)]),
         "clbm_batch_macros": (st, [_VP, ctypes.c_int, _FP, _FP, _FP, _FP]),
         "clbm_batch_residual": (st, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+        "clbm_batch_diagnostics": (st, [_VP, ctypes.c_int, ctypes.POINTER(clbm_diag)]),
         "clbm_batch_autotune": (st, [_VP, ctypes.c_int, ctypes.c_char_p,
                                      ctypes.POINTER(clbm_batch_launch)]),
         "clbm_batch_set_launch": (st, [_VP, ctypes.POINTER(clbm_batch_launch)]),
@@ -391,6 +420,13 @@ class Batch:
         _check(lib().clbm_batch_macros(self._h, int(i), *[_addr(t) for t in out]), "clbm_batch_macros")
         return tuple(out)
 
+    def diagnostics(self, i):
+        d = clbm_diag()
+        st = lib().clbm_batch_diagnostics(self._h, int(i), ctypes.byref(d))
+        if st not in (CLBM_OK, CLBM_ERR_NAN):
+            _check(st, "clbm_batch_diagnostics")
+        return d
+
     def residual(self, i):
         out = (ctypes.c_double * 2)()
         _check(lib().clbm_batch_residual(self._h, int(i), out), "clbm_batch_residual")
@@ -417,6 +453,115 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Net:
+    """The warm-start encoder-decoder on the GPU (BF16 MFMA kernels, FP32 master weights).
+    Parameters are a flat float32 tensor in the canonical order of include/clbm.h."""
+
+    def __init__(self, batch, height, width, cin, cout, widths, device="cuda", stream=None):
+        import torch
+        self.device = torch.device(device)
+        self.desc = clbm_net_desc(int(batch), int(height), int(width), int(cin), int(cout),
+                                  (ctypes.c_int * 4)(*[int(w) for w in widths]))
+        self.shape_in = (int(batch), int(cin), int(height), int(width))
+        self.shape_out = (int(batch), int(cout), int(height), int(width))
+        n = ctypes.c_size_t()
+        _check(lib().clbm_net_param_count(ctypes.byref(self.desc), ctypes.byref(n)), "clbm_net_param_count")
+        self.nparams = n.value
+        _check(lib().clbm_net_workspace_bytes(ctypes.byref(self.desc), ctypes.byref(n)),
+               "clbm_net_workspace_bytes")
+        self.workspace = _workspace(n.value, self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(lib().clbm_net_create(ctypes.byref(self.desc), _addr(self.workspace), self.workspace.numel(),
+                                     _stream_ptr(self.stream), ctypes.byref(h)), "clbm_net_create")
+        self._h = h
+
+    def set_params(self, params):
+        import torch
+        t = torch.as_tensor(params, dtype=torch.float32, device=self.device).contiguous()
+        assert t.numel() == self.nparams
+        _check(lib().clbm_net_set_params(self._h, _addr(t)), "clbm_net_set_params")
+        self._keep_params = t
+
+    def params(self):
+        import torch
+        t = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
+        _check(lib().clbm_net_get_params(self._h, _addr(t)), "clbm_net_get_params")
+        return t
+
+    def grads(self):
+        import torch
+        t = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
+        _check(lib().clbm_net_get_grads(self._h, _addr(t)), "clbm_net_get_grads")
+        return t
+
+    def forward(self, x):
+        import torch
+        x = torch.as_tensor(x, dtype=torch.float32, device=self.device).contiguous()
+        assert tuple(x.shape) == self.shape_in, (x.shape, self.shape_in)
+        y = torch.empty(self.shape_out, dtype=torch.float32, device=self.device)
+        _check(lib().clbm_net_forward(self._h, _addr(x), _addr(y)), "clbm_net_forward")
+        self._keep_x = x
+        return y
+
+    def backward(self, target):
+        import torch
+        t = torch.as_tensor(target, dtype=torch.float32, device=self.device).contiguous()
+        assert tuple(t.shape) == self.shape_out
+        loss = ctypes.c_double()
+        _check(lib().clbm_net_backward(self._h, _addr(t), ctypes.byref(loss)), "clbm_net_backward")
+        return loss.value
+
+    def adam(self, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(lib().clbm_net_adam(self._h, float(lr), float(beta1), float(beta2), float(eps), int(t)),
+               "clbm_net_adam")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().clbm_net_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def resample(src, dh, dw, scale=None, shift=None, stream=None):
+    """Bilinear resampling of float32 fields [nf][sh][sw] (device tensor) to [nf][dh][dw],
+    field f scaled by scale[f] and shifted by shift[f]."""
+    import torch
+    src = src.contiguous()
+    nf, sh, sw = src.shape
+    dst = torch.empty(nf, int(dh), int(dw), dtype=torch.float32, device=src.device)
+    sc = (ctypes.c_float * nf)(*scale) if scale is not None else None
+    sf = (ctypes.c_float * nf)(*shift) if shift is not None else None
+    _check(lib().clbm_resample_bilinear(_addr(src), sh, sw, _addr(dst), int(dh), int(dw), nf, sc, sf,
+                                        _stream_ptr(stream)), "clbm_resample_bilinear")
+    return dst
+
+
+def problem_code(prob):
+    """clbm_problem_code of a problem dict (computed by the library)."""
+    c = clbm_problem_code()
+    _check(lib().clbm_problem_encode(ctypes.byref(make_params(prob)), ctypes.byref(c)),
+           "clbm_problem_encode")
+    return c
+
+
+def features(codes, height, width, device="cuda", stream=None):
+    """Network input planes [len(codes)][8][height][width] from problem codes (device kernel)."""
+    import torch
+    raw = bytes((clbm_problem_code * len(codes))(*codes))
+    d_codes = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+    out = torch.empty(len(codes), 8, int(height), int(width), dtype=torch.float32, device=device)
+    _check(lib().clbm_net_features(_addr(d_codes), len(codes), int(height), int(width), _addr(out),
+                                   _stream_ptr(stream)), "clbm_net_features")
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return out
 
 
 def nusselt(diag, side, H, dT, into_wall=True):

@@ -1,0 +1,165 @@
+// clbm_aux_kernels.h -- kernels around the fused step (gfx950): initial state,
+// macroscopic fields, population export and the diagnostics reductions.
+#pragma once
+
+#include "clbm_kernels.h"
+
+namespace clbm {
+
+// Equilibrium at the given fields followed by one collision: the stored state is
+// the post-collision state at t = 0.
+template <typename S>
+__global__ void __launch_bounds__(256) k_init(S* __restrict__ dst, const LatticeConst c,
+                                              const float* __restrict__ rho,
+                                              const float* __restrict__ ux,
+                                              const float* __restrict__ uy,
+                                              const float* __restrict__ T)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= c.nx || y >= c.ny) return;
+    const size_t k = (size_t)y * c.nx + x;
+    const float drho = rho ? rho[k] - 1.f : 0.f;
+    const float vx = ux ? ux[k] : 0.f;
+    const float vy = uy ? uy[k] : 0.f;
+    const float th = T ? T[k] - c.T0 : 0.f;
+    float a[9], b[5];
+    typename Wide<S>::type tb[5];
+    equilibrium(drho, vx, vy, th, c.T0, a, b);
+    NodeMacro m;
+    collide(c, a, b, tb, m);
+    store_node(dst, c, (unsigned)y * c.pitch + x, a, tb);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_macros(const S* __restrict__ src, const LatticeConst c,
+                                                float* __restrict__ rho, float* __restrict__ ux,
+                                                float* __restrict__ uy, float* __restrict__ T)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= c.nx || y >= c.ny) return;
+    float a[9], b[5];
+    load_own(src, c, (unsigned)y * c.pitch + x, a, b);
+    const NodeMacro m = macros_from_post(c, a, b);
+    const size_t k = (size_t)y * c.nx + x;
+    if (rho) rho[k] = 1.f + m.drho;
+    if (ux) ux[k] = m.ux;
+    if (uy) uy[k] = m.uy;
+    if (T) T[k] = c.T0 + m.theta;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_populations(const S* __restrict__ src, const LatticeConst c,
+                                                     float* __restrict__ f, float* __restrict__ g)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= c.nx || y >= c.ny) return;
+    const unsigned own = (unsigned)y * c.pitch + x;
+    const size_t n = (size_t)c.nx * c.ny, k = (size_t)y * c.nx + x;
+    if (f)
+        for (int i = 0; i < 9; ++i) f[i * n + k] = ld(src + (size_t)i * c.plane + own);
+    if (g)
+        for (int i = 0; i < 5; ++i) g[i * n + k] = ld(src + (size_t)(9 + i) * c.plane + own);
+}
+
+// Diagnostics. Per node: rho - 1, |u|^2, |u - u_snap|^2, T^2, (T - T_snap)^2, NaN flag;
+// per wall node: outward dT/dn (Eq. 27) and T_w (Eq. 28). Sums in FP64: wave64
+// shuffles, then LDS across the waves of the workgroup, then one partial per
+// workgroup; k_diag_final adds the partials in a fixed order.
+constexpr int kDiagSums = 15;  // drho, u2, du2, T2, dT2, dTdn[4], Tw[4], nan, count
+constexpr int kDiagBlock = 256;
+constexpr int kDiagMaxBlocks = 1024;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kDiagBlock) k_diag(const S* __restrict__ src, const LatticeConst c,
+                                                     float* __restrict__ snap, int have_snap,
+                                                     double* __restrict__ partial)
+{
+    double acc[kDiagSums];
+#pragma unroll
+    for (int k = 0; k < kDiagSums; ++k) acc[k] = 0.0;
+    const size_t n = (size_t)c.nx * c.ny;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const unsigned P = c.plane;
+    const S* gs = src + 9 * P;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const int y = (int)(k / c.nx), x = (int)(k - (size_t)y * c.nx);
+        const unsigned own = (unsigned)y * c.pitch + x;
+        float a[9], b[5];
+        load_own(src, c, own, a, b);
+        const NodeMacro m = macros_from_post(c, a, b);
+        const float T = c.T0 + m.theta;
+        const bool bad = !(isfinite(m.drho) && isfinite(m.ux) && isfinite(m.uy) && isfinite(T));
+        acc[0] += m.drho;
+        acc[1] += (double)m.ux * m.ux + (double)m.uy * m.uy;
+        acc[3] += (double)T * T;
+        if (have_snap) {
+            const double dx = m.ux - snap[k], dy = m.uy - snap[n + k], dt = T - snap[2 * n + k];
+            acc[2] += dx * dx + dy * dy;
+            acc[4] += dt * dt;
+        }
+        snap[k] = m.ux;
+        snap[n + k] = m.uy;
+        snap[2 * n + k] = T;
+        acc[13] += bad ? 1.0 : 0.0;
+        // Wall nodes: Eq. (27)-(28) with T1 at the node and T2 one node inward.
+        const bool wall[4] = {!c.periodic_x && x == 0, !c.periodic_x && x == c.nx - 1,
+                              !c.periodic_y && y == 0, !c.periodic_y && y == c.ny - 1};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (!wall[s]) continue;
+            const int x2 = s == 0 ? x + 1 : (s == 1 ? x - 1 : x);
+            const int y2 = s == 2 ? y + 1 : (s == 3 ? y - 1 : y);
+            const unsigned o2 = (unsigned)y2 * c.pitch + x2;
+            float sum2 = 0.f;
+            for (int i = 0; i < 5; ++i) sum2 += ld(gs + i * P + o2);
+            const float th2 = sum2 - 0.5f * c.Q;
+            const float thw = c.a1[s] * m.theta + c.a2[s] * th2 + c.a3[s];
+            acc[5 + s] += (8.0 * thw - 9.0 * m.theta + th2) / 3.0;
+            acc[9 + s] += (double)c.T0 + thw;
+        }
+        acc[14] += 1.0;
+    }
+    __shared__ double lds[kDiagBlock / 64][kDiagSums];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kDiagSums; ++k) {
+        const double v = wave_sum(acc[k]);
+        if (lane == 0) lds[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kDiagSums) {
+        double v = 0.0;
+        for (int w = 0; w < kDiagBlock / 64; ++w) v += lds[w][threadIdx.x];
+        partial[(size_t)blockIdx.x * kDiagSums + threadIdx.x] = v;
+    }
+}
+
+static __global__ void __launch_bounds__(256) k_diag_final(const double* __restrict__ partial, int nparts,
+                                                    double* __restrict__ out)
+{
+    __shared__ double lds[256];
+    for (int k = 0; k < kDiagSums; ++k) {
+        double v = 0.0;
+        for (int p = threadIdx.x; p < nparts; p += blockDim.x) v += partial[(size_t)p * kDiagSums + k];
+        lds[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = lds[0];
+        __syncthreads();
+    }
+}
+
+}  // namespace clbm

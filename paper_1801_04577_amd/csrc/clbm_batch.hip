@@ -13,7 +13,7 @@
 #include <vector>
 
 #include "clbm_host.h"
-#include "clbm_kernels.h"
+#include "clbm_aux_kernels.h"
 
 namespace clbm {
 
@@ -253,6 +253,8 @@ struct clbm_batch {
     int2* d_full;
     int2* d_active;
     double* d_part;
+    double* d_dpart;   // per-instance diagnostics scratch
+    double* d_dres;
     int cap_tiles;
     int total_tiles;
     int parity;
@@ -270,7 +272,7 @@ namespace {
 constexpr int kMinTileX = 64;
 
 struct BatchLayout {
-    size_t inst, status, steps, res, newoff, count, full, active, part, total;
+    size_t inst, status, steps, res, newoff, count, full, active, part, dpart, dres, total;
     std::vector<size_t> buf0, buf1, snap;
     int cap_tiles;
 };
@@ -317,6 +319,8 @@ clbm_status batch_layout(int n, const clbm_params* p, BatchLayout* L)
     L->full = take(sizeof(int2) * cap);
     L->active = take(sizeof(int2) * cap);
     L->part = take(sizeof(double) * kBP * cap);
+    L->dpart = take(sizeof(double) * kDiagMaxBlocks * kDiagSums);
+    L->dres = take(sizeof(double) * kDiagSums);
     L->buf0.resize(n);
     L->buf1.resize(n);
     L->snap.resize(n);
@@ -515,6 +519,8 @@ clbm_status clbm_batch_create(int n, const clbm_params* p, void* d_workspace, si
     b->d_full = (int2*)(ws + L.full);
     b->d_active = (int2*)(ws + L.active);
     b->d_part = (double*)(ws + L.part);
+    b->d_dpart = (double*)(ws + L.dpart);
+    b->d_dres = (double*)(ws + L.dres);
     b->cap_tiles = L.cap_tiles;
     b->launch = lc;
     for (int i = 0; i < n; ++i) {
@@ -614,6 +620,39 @@ clbm_status clbm_batch_macros(clbm_batch* b, int i, float* d_rho, float* d_ux, f
                        (const float*)(uintptr_t)I.buf[b->parity], I.c, d_rho, d_ux, d_uy, d_T);
     CLBM_HIP(hipGetLastError());
     return CLBM_OK;
+}
+
+clbm_status clbm_batch_diagnostics(clbm_batch* b, int i, clbm_diag* out)
+{
+    if (!b || i < 0 || i >= b->n || !out) return CLBM_ERR_INVALID_ARG;
+    const BatchInst& I = b->inst[i];
+    const size_t n = (size_t)I.c.nx * I.c.ny;
+    const int blocks = (int)std::min<size_t>((n + kDiagBlock - 1) / kDiagBlock, kDiagMaxBlocks);
+    hipLaunchKernelGGL(k_diag<float>, dim3(blocks), dim3(kDiagBlock), 0, b->stream,
+                       (const float*)(uintptr_t)I.buf[b->parity], I.c, (float*)(uintptr_t)I.snap, 0,
+                       b->d_dpart);
+    CLBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, b->stream, b->d_dpart, blocks, b->d_dres);
+    CLBM_HIP(hipGetLastError());
+    double r[kDiagSums];
+    CLBM_HIP(hipMemcpyAsync(r, b->d_dres, sizeof r, hipMemcpyDeviceToHost, b->stream));
+    long long st = 0;
+    CLBM_HIP(hipMemcpyAsync(&st, b->d_steps + i, sizeof st, hipMemcpyDeviceToHost, b->stream));
+    CLBM_HIP(hipStreamSynchronize(b->stream));
+    std::memset(out, 0, sizeof *out);
+    out->step = (long)st;
+    out->mass = (double)n + r[0];
+    out->sum_u2 = r[1];
+    out->sum_T2 = r[3];
+    const clbm_params& p = b->p[i];
+    const int len[4] = {p.ny, p.ny, p.nx, p.nx};
+    for (int s = 0; s < 4; ++s) {
+        if (p.side[s].kind != CLBM_WALL) continue;
+        out->dTdn[s] = r[5 + s] / len[s];
+        out->T_wall[s] = r[9 + s] / len[s];
+    }
+    out->nan_count = (long)r[13];
+    return out->nan_count > 0 ? CLBM_ERR_NAN : CLBM_OK;
 }
 
 clbm_status clbm_batch_residual(clbm_batch* b, int i, double out[2])

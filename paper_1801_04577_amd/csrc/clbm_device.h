@@ -63,16 +63,9 @@ __device__ __forceinline__ unsigned mix32(unsigned h)
     return h;
 }
 
-__device__ __forceinline__ double dither_uniform(double x)
-{
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(x);
-    const unsigned h = mix32((unsigned)bits ^ mix32((unsigned)(bits >> 32)));
-    return (double)(h >> 8) * (1.0 / 16777216.0);
-}
-
 // binary16 neighbour of h (value hf) on the side of r, and the dithered choice for a
-// value hf + r.
-__device__ __forceinline__ __half half_dither(__half h, float hf, float r, double u)
+// value hf + r given a uniform variate u in [0, 1).
+__device__ __forceinline__ __half half_dither(__half h, float hf, float r, float u)
 {
     const unsigned short fb = __half_as_ushort(h);
     const bool up = r > 0.f;
@@ -81,7 +74,7 @@ __device__ __forceinline__ __half half_dither(__half h, float hf, float r, doubl
         : ((((fb >> 15) == 0u) == up) ? fb + 1u : fb - 1u));
     const __half g = __ushort_as_half(gb);
     const float gap = __half2float(g) - hf;
-    return fabsf((float)u * gap) < fabsf(r) ? g : h;
+    return fabsf(u * gap) < fabsf(r) ? g : h;
 }
 
 // Flow populations are computed in FP32: stored as is in FP32, and with the dithered
@@ -92,32 +85,28 @@ template <> __device__ __forceinline__ void st<__half>(__half* p, float v)
 {
     const __half h = __float2half_rn(v);
     const float hf = __half2float(h);
-    const unsigned hb = mix32(__float_as_uint(v) ^ 0x9e3779b9u);
-    *p = half_dither(h, hf, v - hf, (double)(hb >> 8) * (1.0 / 16777216.0));
+    const unsigned hb = mix32(__float_as_uint(v));
+    *p = half_dither(h, hf, v - hf, (float)(hb >> 8) * (1.0f / 16777216.0f));
 }
 
-template <typename S> __device__ __forceinline__ void st_dither(S* p, double x);
+// Storage of the temperature populations: evaluated in FP64 registers for FP32 storage
+// and in FP32 for binary16 storage (whose rounding, 2^-11, dominates FP32's).
+template <typename S> struct Wide;
+template <> struct Wide<float> { typedef double type; };
+template <> struct Wide<__half> { typedef float type; };
+
+template <typename S> __device__ __forceinline__ void st_dither(S* p, typename Wide<S>::type x);
+// FP64 -> FP32: add a hashed 29-bit offset to the 52-bit mantissa and truncate the 29 bits
+// FP32 does not keep; the conversion of the truncated value is then exact. The magnitude
+// rounds up with probability (discarded bits)/2^29, so the expected stored value is x.
 template <> __device__ __forceinline__ void st_dither<float>(float* p, double x)
 {
-    const float f = (float)x;
-    const double r = x - (double)f;
-    const unsigned fb = __float_as_uint(f);
-    const bool up = r > 0.0;
-    // neighbour of f in the direction of r (sign-magnitude bit pattern)
-    const unsigned gb = (fb << 1) == 0u ? (up ? 1u : 0x80000001u)
-                                         : (((fb >> 31) == 0u) == up ? fb + 1u : fb - 1u);
-    const float g = __uint_as_float(gb);
-    const double gap = (double)g - (double)f;
-    const float v = fabs(dither_uniform(x) * gap) < fabs(r) ? g : f;
-    __builtin_nontemporal_store(v, p);
+    unsigned long long bits = (unsigned long long)__double_as_longlong(x);
+    bits += (unsigned long long)(mix32((unsigned)bits) >> 3);
+    bits &= ~0x1FFFFFFFull;
+    __builtin_nontemporal_store((float)__longlong_as_double((long long)bits), p);
 }
-template <> __device__ __forceinline__ void st_dither<__half>(__half* p, double x)
-{
-    const float xf = (float)x;
-    const __half h = __float2half_rn(xf);
-    const float hf = __half2float(h);
-    *p = half_dither(h, hf, xf - hf, dither_uniform(x));
-}
+template <> __device__ __forceinline__ void st_dither<__half>(__half* p, float x) { st<__half>(p, x); }
 
 struct NodeMacro {
     float drho;   // rho - 1
@@ -131,49 +120,51 @@ struct NodeMacro {
 // unbiased one into storage: a heat source adds the same non-representable amount
 // every step, and round-to-nearest of that increment onto the storage grid would
 // otherwise bias the temperature by a fixed fraction of an ulp per step.
+template <typename R>
 __device__ __forceinline__ void collide_thermal(const LatticeConst& c, const float b[5], float uxf,
-                                                float uyf, double tb[5])
+                                                float uyf, R tb[5])
 {
-    const double ux = uxf, uy = uyf, Q = c.Q, T0 = c.T0;
-    const double b0 = b[0], b1 = b[1], b2 = b[2], b3 = b[3], b4 = b[4];
-    const double ux2 = ux * ux, uy2 = uy * uy;
+    const R ux = uxf, uy = uyf, Q = c.Q, T0 = c.T0;
+    const R b0 = b[0], b1 = b[1], b2 = b[2], b3 = b[3], b4 = b[4];
+    const R ux2 = ux * ux, uy2 = uy * uy;
     // Raw moments of b (Eq. 16); the rest weights carry [T0, 0, 0, T0 c_T^2, T0 c_T^2].
-    const double sb = (b0 + b1) + (b2 + b3) + b4;
-    const double theta = sb + 0.5 * Q;               // Eq. (25), minus T0
-    const double t10 = b1 - b3, t01 = b2 - b4, t20 = b1 + b3, t02 = b2 + b4;
-    const double K00 = T0 + sb;                      // full raw k00 = T - Q/2
+    const R sb = (b0 + b1) + (b2 + b3) + b4;
+    const R theta = sb + R(0.5) * Q;               // Eq. (25), minus T0
+    const R t10 = b1 - b3, t01 = b2 - b4, t20 = b1 + b3, t02 = b2 + b4;
+    const R K00 = T0 + sb;                      // full raw k00 = T - Q/2
     // Central moments (Eq. 17) minus equilibria (Eq. 19).
-    const double e10 = t10 - ux * K00;
-    const double e01 = t01 - uy * K00;
-    const double m20 = t20 - 0.4 * theta - 2.0 * ux * t10 + ux2 * K00;
-    const double m02 = t02 - 0.4 * theta - 2.0 * uy * t01 + uy2 * K00;
+    const R e10 = t10 - ux * K00;
+    const R e01 = t01 - uy * K00;
+    const R m20 = t20 - R(0.4) * theta - R(2.0) * ux * t10 + ux2 * K00;
+    const R m02 = t02 - R(0.4) * theta - R(2.0) * uy * t01 + uy2 * K00;
     // Eq. (23): k00 relaxes to T + Q/2 for any lambda_0; lambda_1 on k10, k01;
     // lambda_2 on k20, k02 with the source (1 - lambda_2/2) c_T^2 Q.
-    const double e10s = (double)c.one_m_l1 * e10;
-    const double e01s = (double)c.one_m_l1 * e01;
-    const double m20s = (double)c.one_m_l2 * m20 + (double)c.src2;
-    const double m02s = (double)c.one_m_l2 * m02 + (double)c.src2;
+    const R e10s = (R)c.one_m_l1 * e10;
+    const R e01s = (R)c.one_m_l1 * e01;
+    const R m20s = (R)c.one_m_l2 * m20 + (R)c.src2;
+    const R m02s = (R)c.one_m_l2 * m02 + (R)c.src2;
     // Back to raw moments (shift by -u): k00* = T + Q/2 = T0 + Th.
-    const double Th = theta + 0.5 * Q;
-    const double K00s = T0 + Th;
-    const double q10 = e10s + ux * K00s;
-    const double q01 = e01s + uy * K00s;
-    const double q20 = 0.4 * theta + m20s + 2.0 * ux * e10s + ux2 * K00s;   // k20* - T0 c_T^2
-    const double q02 = 0.4 * theta + m02s + 2.0 * uy * e01s + uy2 * K00s;
+    const R Th = theta + R(0.5) * Q;
+    const R K00s = T0 + Th;
+    const R q10 = e10s + ux * K00s;
+    const R q01 = e01s + uy * K00s;
+    const R q20 = R(0.4) * theta + m20s + R(2.0) * ux * e10s + ux2 * K00s;   // k20* - T0 c_T^2
+    const R q02 = R(0.4) * theta + m02s + R(2.0) * uy * e01s + uy2 * K00s;
     // Inverse of Eq. (16).
     tb[0] = Th - q20 - q02;
-    tb[1] = 0.5 * (q20 + q10);
-    tb[3] = 0.5 * (q20 - q10);
-    tb[2] = 0.5 * (q02 + q01);
-    tb[4] = 0.5 * (q02 - q01);
+    tb[1] = R(0.5) * (q20 + q10);
+    tb[3] = R(0.5) * (q20 - q10);
+    tb[2] = R(0.5) * (q02 + q01);
+    tb[4] = R(0.5) * (q02 - q01);
 }
 
 // Cascaded collision of one node. On entry a[9], b[5] hold the pre-collision
 // deviations at time t; on exit a[9] holds the post-collision flow deviations and
-// tb[5] the post-collision temperature deviations (in FP64, to be rounded into
-// storage by store_node). m receives rho - 1, u and T - T0 at time t.
-__device__ __forceinline__ void collide(const LatticeConst& c, float a[9], const float b[5],
-                                        double tb[5], NodeMacro& m)
+// tb[5] the post-collision temperature deviations (in the wide type R, to be rounded
+// into storage by store_node). m receives rho - 1, u and T - T0 at time t.
+template <typename R>
+__device__ __forceinline__ void collide(const LatticeConst& c, float a[9], const float b[5], R tb[5],
+                                        NodeMacro& m)
 {
     // Eq. (25): T = sum g + Q/2; sum g = T0 + sum b.
     const float sb = (b[0] + b[1]) + (b[2] + b[3]) + b[4];

@@ -96,10 +96,11 @@ __device__ __forceinline__ void gather_node(const S* __restrict__ src, const Lat
 }
 
 // Store the post-collision state of one node: flow deviations rounded to nearest,
-// temperature deviations (FP64 on entry) with the unbiased rounding of st_dither.
+// temperature deviations (computed wider than the storage) with the unbiased rounding of
+// st_dither.
 template <typename S>
 __device__ __forceinline__ void store_node(S* __restrict__ dst, const LatticeConst& c, unsigned own,
-                                           const float a[9], const double tb[5])
+                                           const float a[9], const typename Wide<S>::type tb[5])
 {
     const unsigned P = c.plane;
 #pragma unroll
@@ -146,71 +147,13 @@ __global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __r
         const int y = y0 + r;
         if (y < c.ny) {
             float a[9], b[5];
-            double tb[5];
+            typename Wide<S>::type tb[5];
             gather_node(src, c, x, y, a, b);
             NodeMacro m;
             collide(c, a, b, tb, m);
             store_node(dst, c, (unsigned)y * c.pitch + x, a, tb);
         }
     }
-}
-
-// Equilibrium at the given fields followed by one collision: the stored state is
-// the post-collision state at t = 0.
-template <typename S>
-__global__ void __launch_bounds__(256) k_init(S* __restrict__ dst, const LatticeConst c,
-                                              const float* __restrict__ rho,
-                                              const float* __restrict__ ux,
-                                              const float* __restrict__ uy,
-                                              const float* __restrict__ T)
-{
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    if (x >= c.nx || y >= c.ny) return;
-    const size_t k = (size_t)y * c.nx + x;
-    const float drho = rho ? rho[k] - 1.f : 0.f;
-    const float vx = ux ? ux[k] : 0.f;
-    const float vy = uy ? uy[k] : 0.f;
-    const float th = T ? T[k] - c.T0 : 0.f;
-    float a[9], b[5];
-    double tb[5];
-    equilibrium(drho, vx, vy, th, c.T0, a, b);
-    NodeMacro m;
-    collide(c, a, b, tb, m);
-    store_node(dst, c, (unsigned)y * c.pitch + x, a, tb);
-}
-
-template <typename S>
-__global__ void __launch_bounds__(256) k_macros(const S* __restrict__ src, const LatticeConst c,
-                                                float* __restrict__ rho, float* __restrict__ ux,
-                                                float* __restrict__ uy, float* __restrict__ T)
-{
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    if (x >= c.nx || y >= c.ny) return;
-    float a[9], b[5];
-    load_own(src, c, (unsigned)y * c.pitch + x, a, b);
-    const NodeMacro m = macros_from_post(c, a, b);
-    const size_t k = (size_t)y * c.nx + x;
-    if (rho) rho[k] = 1.f + m.drho;
-    if (ux) ux[k] = m.ux;
-    if (uy) uy[k] = m.uy;
-    if (T) T[k] = c.T0 + m.theta;
-}
-
-template <typename S>
-__global__ void __launch_bounds__(256) k_populations(const S* __restrict__ src, const LatticeConst c,
-                                                     float* __restrict__ f, float* __restrict__ g)
-{
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    if (x >= c.nx || y >= c.ny) return;
-    const unsigned own = (unsigned)y * c.pitch + x;
-    const size_t n = (size_t)c.nx * c.ny, k = (size_t)y * c.nx + x;
-    if (f)
-        for (int i = 0; i < 9; ++i) f[i * n + k] = ld(src + (size_t)i * c.plane + own);
-    if (g)
-        for (int i = 0; i < 5; ++i) g[i * n + k] = ld(src + (size_t)(9 + i) * c.plane + own);
 }
 
 }  // namespace clbm

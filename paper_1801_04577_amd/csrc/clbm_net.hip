@@ -1,0 +1,998 @@
+// clbm_net.hip -- the warm-start network on gfx950: a four-level convolutional
+// encoder-decoder with skip connections, trained and run by the library's own
+// kernels. 3x3 convolutions are implicit GEMMs on BF16 MFMA
+// (v_mfma_f32_16x16x32_bf16) with FP32 accumulation; activations and activation
+// gradients are BF16 in NHWC layout, master weights, weight gradients and the Adam
+// state are FP32.
+//
+// Layer order (15 convolutions, widths w1..w4, input planes cin, output fields cout):
+//   0: cin->w1   1: w1->w1 (= s1)                       at H x W
+//   2: w1->w2    3: w2->w2 (= s2)      after avg-pool   at H/2
+//   4: w2->w3    5: w3->w3 (= s3)      after avg-pool   at H/4
+//   6: w3->w4    7: w4->w4             after avg-pool   at H/8
+//   8: (w4+w3)->w3  9: w3->w3   on concat[up(h), s3]    at H/4
+//  10: (w3+w2)->w2 11: w2->w2   on concat[up(h), s2]    at H/2
+//  12: (w2+w1)->w1 13: w1->w1   on concat[up(h), s1]    at H
+//  14: w1->cout (no activation)
+// Every convolution but the last is followed by ReLU. The concatenations are free:
+// the skip tensor is written straight into the upper channel range of the buffer the
+// decoder reads. The canonical parameter vector stores, per layer in this order,
+// W[cout][cin][3][3] then b[cout] (FP32).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "clbm_host.h"
+
+namespace clbm {
+
+typedef __bf16 bf16;
+typedef bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kLayers = 15;
+constexpr int kKChunk = 32;  // K per MFMA (one 3x3 tap, 32 input channels)
+
+__device__ __forceinline__ float bf2f(bf16 v) { return (float)v; }
+__device__ __forceinline__ bf16 f2bf(float v) { return (bf16)v; }
+
+// ---------------------------------------------------------------------------
+// Implicit-GEMM 3x3 convolution (zero padding 1), one output pixel row of the GEMM
+// per image pixel: M = B*H*W pixels, N = output channels, K = 9 taps x Cin.
+// A workgroup of 4 waves covers 64 pixels x (16*NB) channels; each wave 16 pixels.
+// MFMA 16x16x32 operand layout: lane l holds row (l % 16) of A and column (l % 16)
+// of B, elements k = 8*(l/16) .. 8*(l/16)+7; the result holds column (l % 16),
+// rows 4*(l/16) .. 4*(l/16)+3.
+// mode 0: y = bf16(relu(acc + bias)); mode 1: y = bf16(acc) (input gradients);
+// mode 2: fp32 NCHW output yf = acc + bias (network output, n < N only).
+// ---------------------------------------------------------------------------
+template <int NB>
+__global__ void __launch_bounds__(256) k_conv(const bf16* __restrict__ x, int xC, int xoff, int Cin,
+                                              const bf16* __restrict__ w,
+                                              const float* __restrict__ bias, int N, int H, int W,
+                                              int mode, bf16* __restrict__ y, int yC, int yoff,
+                                              float* __restrict__ yf)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int HW = H * W;
+    const int p0 = blockIdx.x * 64 + wave * 16;
+    const int n0 = blockIdx.y * (16 * NB);
+    const int pa = p0 + (lane & 15);
+    const int b = pa / HW, rem = pa - b * HW, py = rem / W, px = rem - py * W;
+    const int kq = (lane >> 4) * 8;
+    f32x4 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero = {};
+    for (int tap = 0; tap < 9; ++tap) {
+        const int sy = py + tap / 3 - 1, sx = px + tap % 3 - 1;
+        const bool in = sy >= 0 && sy < H && sx >= 0 && sx < W;
+        // clamped source so the address is valid even where the value is not used
+        const int cy = min(max(sy, 0), H - 1), cx = min(max(sx, 0), W - 1);
+        const bf16* xs = x + (size_t)(b * HW + cy * W + cx) * xC + xoff + kq;
+        for (int c0 = 0; c0 < Cin; c0 += kKChunk) {
+            bf16x8 a = *reinterpret_cast<const bf16x8*>(xs + c0);
+            if (!in) a = zero;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int n = n0 + 16 * nb + (lane & 15);
+                const bf16x8 bw =
+                    *reinterpret_cast<const bf16x8*>(w + ((size_t)n * 9 + tap) * Cin + c0 + kq);
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[nb], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int n = n0 + 16 * nb + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int p = p0 + 4 * (lane >> 4) + v;
+            float r = acc[nb][v];
+            if (mode == 2) {
+                if (n < N) {
+                    const int bb = p / HW, rr = p - bb * HW;
+                    yf[((size_t)bb * N + n) * HW + rr] = r + bias[n];
+                }
+            } else if (n < N) {
+                if (mode == 0) r = fmaxf(r + bias[n], 0.f);
+                y[(size_t)p * yC + yoff + n] = f2bf(r);
+            }
+        }
+    }
+}
+
+// Weight gradient of one 3x3 convolution over a range of pixels (split-K):
+// part[s][co][tap][ci] = sum over pixels p of the split of dz[p][co] * x[src(p,tap)][ci].
+// One wave per (16 co x 16 ci) tile and tap; MFMA A = dz^T (co x pixels), B = shifted x
+// (pixels x ci); operands gathered element-wise (the reduction runs over pixels,
+// which are strided in NHWC).
+__global__ void __launch_bounds__(64) k_wgrad(const bf16* __restrict__ dz, int zC, int Cout,
+                                              const bf16* __restrict__ x, int xC, int xoff, int Cin,
+                                              int H, int W, int P, int pix_per_split,
+                                              float* __restrict__ part)
+{
+    const int lane = threadIdx.x;
+    const int tiles_ci = Cin / 16;
+    const int co0 = (blockIdx.x / tiles_ci) * 16, ci0 = (blockIdx.x % tiles_ci) * 16;
+    const int tap = blockIdx.y, split = blockIdx.z;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int HW = H * W;
+    const int pbeg = split * pix_per_split, pend = min(P, pbeg + pix_per_split);
+    const int co = co0 + (lane & 15), ci = ci0 + (lane & 15), kq = (lane >> 4) * 8;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int pk = pbeg; pk < pend; pk += kKChunk) {
+        bf16x8 a, bv;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int p = pk + kq + j;
+            float av = 0.f, xv = 0.f;
+            if (p < pend) {
+                av = bf2f(dz[(size_t)p * zC + co]);
+                const int b = p / HW, rem = p - b * HW, py = rem / W, px = rem - py * W;
+                const int sy = py + dy, sx = px + dx;
+                if (sy >= 0 && sy < H && sx >= 0 && sx < W)
+                    xv = bf2f(x[(size_t)(b * HW + sy * W + sx) * xC + xoff + ci]);
+            }
+            a[j] = f2bf(av);
+            bv[j] = f2bf(xv);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc, 0, 0, 0);
+    }
+    float* out = part + (size_t)split * Cout * 9 * Cin;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = co0 + 4 * (lane >> 4) + v;   // row of the result = output channel
+        out[((size_t)r * 9 + tap) * Cin + ci] = acc[v];
+    }
+}
+
+// Sum of the split partials in split order, written in the canonical layout
+// grad[co][ci][ky][kx] for co < Cout_real, ci < Cin_real (the partials use the padded
+// strides Cout, Cin).
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int splits, int Cout, int Cin,
+                               int Cout_real, int Cin_real, float* __restrict__ grad)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int total = Cout_real * 9 * Cin_real;
+    if (k >= total) return;
+    const int co = k / (9 * Cin_real), r = k - co * 9 * Cin_real;
+    const int ci = r / 9, tap = r - ci * 9;
+    float s = 0.f;
+    for (int sp = 0; sp < splits; ++sp) s += part[(((size_t)sp * Cout + co) * 9 + tap) * Cin + ci];
+    grad[k] = s;
+}
+
+// Bias gradient: db[c] = sum over pixels of dz[p][c]; block (64 channels x 4 rows),
+// one partial per block row of pixels, then a fixed-order sum over the splits.
+__global__ void __launch_bounds__(256) k_bias_grad(const bf16* __restrict__ dz, int zC, int C, int P,
+                                                   int pix_per_split, float* __restrict__ part)
+{
+    __shared__ float lds[4][64];
+    const int c = blockIdx.x * 64 + threadIdx.x;
+    const int split = blockIdx.y;
+    const int pbeg = split * pix_per_split, pend = min(P, pbeg + pix_per_split);
+    float s = 0.f;
+    if (c < C)
+        for (int p = pbeg + threadIdx.y; p < pend; p += 4) s += bf2f(dz[(size_t)p * zC + c]);
+    lds[threadIdx.y][threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.y == 0 && c < C)
+        part[(size_t)split * C + c] = (lds[0][threadIdx.x] + lds[1][threadIdx.x]) +
+                                      (lds[2][threadIdx.x] + lds[3][threadIdx.x]);
+}
+
+__global__ void k_bias_reduce(const float* __restrict__ part, int splits, int C, float* __restrict__ g)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    float s = 0.f;
+    for (int sp = 0; sp < splits; ++sp) s += part[(size_t)sp * C + c];
+    g[c] = s;
+}
+
+// Canonical FP32 weights -> BF16 forward layout wf[n][tap][ci] (n < Npad, ci < CinPad,
+// zeros outside the real sizes) and the input-gradient layout wb[ci][tap'][co] with
+// tap' = 8 - tap (the transposed, flipped kernel).
+__global__ void k_weight_prep(const float* __restrict__ Wc, int Cout, int Cin, int NoutPad,
+                              int CinPad, int CoutKPad, bf16* __restrict__ wf, bf16* __restrict__ wb)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nf = NoutPad * 9 * CinPad;
+    if (k < nf) {
+        const int n = k / (9 * CinPad), r = k - n * 9 * CinPad;
+        const int tap = r / CinPad, ci = r - tap * CinPad;
+        const float v = (n < Cout && ci < Cin) ? Wc[((size_t)n * Cin + ci) * 9 + tap] : 0.f;
+        wf[k] = f2bf(v);
+    }
+    if (wb) {
+        const int nb = CinPad * 9 * CoutKPad;
+        if (k < nb) {
+            const int ci = k / (9 * CoutKPad), r = k - ci * 9 * CoutKPad;
+            const int tp = r / CoutKPad, co = r - tp * CoutKPad;
+            const int tap = 8 - tp;
+            const float v = (co < Cout && ci < Cin) ? Wc[((size_t)co * Cin + ci) * 9 + tap] : 0.f;
+            wb[k] = f2bf(v);
+        }
+    }
+}
+
+// fp32 NCHW input planes -> bf16 NHWC with zero channel padding.
+__global__ void k_pack_input(const float* __restrict__ xin, int Cin, int HW, int P,
+                             bf16* __restrict__ x, int xC)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P * xC) return;
+    const int p = k / xC, c = k - p * xC;
+    const int b = p / HW, r = p - b * HW;
+    x[k] = f2bf(c < Cin ? xin[((size_t)b * Cin + c) * HW + r] : 0.f);
+}
+
+// 2x2 average pooling and nearest 2x upsampling on channel views.
+__global__ void k_avgpool(const bf16* __restrict__ x, int xC, int xoff, int C, int H, int W,
+                          int B, bf16* __restrict__ y, int yC, int yoff)
+{
+    const int Ho = H / 2, Wo = W / 2;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= B * Ho * Wo * C) return;
+    const int c = k % C, p = k / C;
+    const int b = p / (Ho * Wo), r = p - b * Ho * Wo, oy = r / Wo, ox = r - oy * Wo;
+    const size_t base = (size_t)b * H * W;
+    const float s = bf2f(x[(base + (2 * oy) * W + 2 * ox) * xC + xoff + c]) +
+                    bf2f(x[(base + (2 * oy) * W + 2 * ox + 1) * xC + xoff + c]) +
+                    bf2f(x[(base + (2 * oy + 1) * W + 2 * ox) * xC + xoff + c]) +
+                    bf2f(x[(base + (2 * oy + 1) * W + 2 * ox + 1) * xC + xoff + c]);
+    y[(size_t)p * yC + yoff + c] = f2bf(0.25f * s);
+}
+
+__global__ void k_upsample(const bf16* __restrict__ x, int xC, int xoff, int C, int H, int W, int B,
+                           bf16* __restrict__ y, int yC, int yoff)
+{
+    // x is H x W, y is 2H x 2W
+    const int Ho = 2 * H, Wo = 2 * W;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= B * Ho * Wo * C) return;
+    const int c = k % C, p = k / C;
+    const int b = p / (Ho * Wo), r = p - b * Ho * Wo, oy = r / Wo, ox = r - oy * Wo;
+    y[(size_t)p * yC + yoff + c] = x[((size_t)b * H * W + (oy / 2) * W + ox / 2) * xC + xoff + c];
+}
+
+// Gradient of the nearest upsampling: 2x2 sums (dy is 2H x 2W, dx is H x W).
+__global__ void k_upsample_bwd(const bf16* __restrict__ dy, int dyC, int dyoff, int C, int H, int W,
+                               int B, bf16* __restrict__ dx, int dxC, int dxoff)
+{
+    const int Wi = 2 * W;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= B * H * W * C) return;
+    const int c = k % C, p = k / C;
+    const int b = p / (H * W), r = p - b * H * W, oy = r / W, ox = r - oy * W;
+    const size_t base = (size_t)b * 4 * H * W;
+    const float s = bf2f(dy[(base + (2 * oy) * Wi + 2 * ox) * dyC + dyoff + c]) +
+                    bf2f(dy[(base + (2 * oy) * Wi + 2 * ox + 1) * dyC + dyoff + c]) +
+                    bf2f(dy[(base + (2 * oy + 1) * Wi + 2 * ox) * dyC + dyoff + c]) +
+                    bf2f(dy[(base + (2 * oy + 1) * Wi + 2 * ox + 1) * dyC + dyoff + c]);
+    dx[(size_t)p * dxC + dxoff + c] = f2bf(s);
+}
+
+// dz = (dskip + pool_backward(dpool)) * (a > 0), all at H x W; dpool is H/2 x W/2.
+// With dskip == nullptr and dpool == nullptr it is the plain ReLU gradient dz = dy * (a > 0)
+// where dy is passed as dskip.
+__global__ void k_relu_grad(const bf16* __restrict__ dskip, int sC, int soff,
+                            const bf16* __restrict__ dpool, int pC, const bf16* __restrict__ a,
+                            int aC, int aoff, int C, int H, int W, int B, bf16* __restrict__ dz,
+                            int zC)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= B * H * W * C) return;
+    const int c = k % C, p = k / C;
+    float g = dskip ? bf2f(dskip[(size_t)p * sC + soff + c]) : 0.f;
+    if (dpool) {
+        const int b = p / (H * W), r = p - b * H * W, py = r / W, px = r - py * W;
+        const int Wo = W / 2;
+        g += 0.25f * bf2f(dpool[((size_t)b * (H / 2) * Wo + (py / 2) * Wo + px / 2) * pC + c]);
+    }
+    const float av = bf2f(a[(size_t)p * aC + aoff + c]);
+    dz[(size_t)p * zC + c] = f2bf(av > 0.f ? g : 0.f);
+}
+
+// Mean squared error: dy = 2 (y - t)/n into a bf16 NHWC buffer (zero channel padding),
+// per-block sums of (y - t)^2 in FP64.
+__global__ void __launch_bounds__(256) k_mse(const float* __restrict__ yv, const float* __restrict__ t,
+                                             int Cout, int HW, int P, int zC, double inv_n,
+                                             bf16* __restrict__ dz, double* __restrict__ part)
+{
+    __shared__ double lds[256];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (k < P * zC) {
+        const int p = k / zC, c = k - p * zC;
+        float g = 0.f;
+        if (c < Cout) {
+            const int b = p / HW, r = p - b * HW;
+            const size_t i = ((size_t)b * Cout + c) * HW + r;
+            const double d = (double)yv[i] - (double)t[i];
+            s = d * d;
+            g = (float)(2.0 * d * inv_n);
+        }
+        dz[k] = f2bf(g);
+    }
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) lds[threadIdx.x] += lds[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = lds[0];
+}
+
+__global__ void k_sum_d(const double* __restrict__ part, int n, double* __restrict__ out)
+{
+    __shared__ double lds[256];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) s += part[k];
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) lds[threadIdx.x] += lds[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = lds[0];
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, size_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2)
+{
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.f - b1) * gk;
+    const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    p[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+// Bilinear resampling of nf fields [nf][sh][sw] onto [nf][dh][dw] (cell-centred grids,
+// edge values held), dst = scale[f] * value + shift[f].
+struct FieldAffine {
+    float scale[16], shift[16];
+};
+
+__global__ void k_resample(const float* __restrict__ src, int sh, int sw, float* __restrict__ dst,
+                           int dh, int dw, int nf, FieldAffine af)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nf * dh * dw) return;
+    const int f = k / (dh * dw), r = k - f * dh * dw, y = r / dw, x = r - y * dw;
+    const float fy = fminf(fmaxf((y + 0.5f) * sh / dh - 0.5f, 0.f), (float)(sh - 1));
+    const float fx = fminf(fmaxf((x + 0.5f) * sw / dw - 0.5f, 0.f), (float)(sw - 1));
+    const int y0 = (int)fy, x0 = (int)fx;
+    const int y1 = min(y0 + 1, sh - 1), x1 = min(x0 + 1, sw - 1);
+    const float ty = fy - y0, tx = fx - x0;
+    const float* s = src + (size_t)f * sh * sw;
+    const float v = (1.f - ty) * ((1.f - tx) * s[y0 * sw + x0] + tx * s[y0 * sw + x1]) +
+                    ty * ((1.f - tx) * s[y1 * sw + x0] + tx * s[y1 * sw + x1]);
+    dst[k] = af.scale[f] * v + af.shift[f];
+}
+
+// Input planes of the warm-start network for one problem per sample (see
+// clbm_net_features in include/clbm.h for the channel list).
+__global__ void k_features(const clbm_problem_code* __restrict__ codes, int B, int H, int W,
+                           float* __restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= B * H * W) return;
+    const int b = k / (H * W), r = k - b * H * W, y = r / W, x = r - y * W;
+    const clbm_problem_code c = codes[b];
+    // boundary cells of the network grid, side order x-, x+, y-, y+
+    const bool at[4] = {x == 0, x == W - 1, y == 0, y == H - 1};
+    float tw = 0.f, dir = 0.f, neu = 0.f;
+    for (int s = 0; s < 4; ++s) {
+        if (!at[s]) continue;
+        if (c.kind[s] == 1) { dir = 1.f; tw = c.theta_wall[s]; }
+        if (c.kind[s] == 2) neu = 1.f;
+    }
+    float* o = out + (size_t)b * 8 * H * W + r;
+    const size_t pl = (size_t)H * W;
+    o[0] = (c.log10_ra - 4.5f) / 1.5f;
+    o[pl] = (c.pr - 3.85f) / 3.15f;
+    o[2 * pl] = c.q_star / 4.f;
+    o[3 * pl] = tw;
+    o[4 * pl] = dir;
+    o[5 * pl] = neu;
+    o[6 * pl] = 2.f * (x + 0.5f) / W - 1.f;
+    o[7 * pl] = c.log2_aspect;
+}
+
+}  // namespace clbm
+
+using namespace clbm;
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct TView {
+    bf16* p;
+    int C;    // channel stride
+    int off;  // channel offset
+};
+
+struct Layer {
+    int cin, cout;       // real sizes
+    int cin_pad;         // K channels (multiple of 32)
+    int nout_pad;        // forward N (multiple of 16 * NB)
+    int nb;              // 16-channel blocks per wave in the forward
+    int cout_kpad;       // K channels of the input-gradient convolution (multiple of 32)
+    int H, W;            // resolution it runs at
+    size_t woff, boff;   // offsets of W and b in the canonical vector
+    bf16* wf;
+    bf16* wb;
+    TView in, out;       // forward input and output views
+    TView dz;            // gradient w.r.t. the pre-activation (and output) of the layer
+    TView din;           // gradient w.r.t. the input (nullptr p for layer 0)
+};
+
+int round_up(int v, int a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct clbm_net {
+    clbm_net_desc d;
+    hipStream_t stream;
+    Layer L[kLayers];
+    size_t nparams;
+    float *params, *grads, *adam_m, *adam_v;
+    float* wpart;      // weight-gradient split partials
+    size_t wpart_floats;
+    float* bpart;      // bias-gradient partials
+    double* lpart;     // loss partials
+    double* loss;
+    bf16* xin;         // packed input (cin padded)
+    float* yout;       // network output fp32 NCHW
+    bf16* dyout;       // loss gradient (cout padded to 32)
+    // activations
+    bf16 *a1, *cat1, *p1, *a2, *cat2, *p2, *a3, *cat3, *p3, *a4, *m4, *d3a, *d3b, *d2a, *d2b, *d1a, *d1b;
+    // activation gradients
+    bf16 *g_d1b, *g_d1a, *g_cat1, *g_d2b, *g_d2a, *g_cat2, *g_d3b, *g_d3a, *g_cat3, *g_m4, *g_a4, *g_p3,
+        *g_a3, *g_p2, *g_a2, *g_p1, *g_a1, *g_z;  // g_z: scratch for dz of the current layer
+    size_t zscratch;
+    int weights_stale;
+};
+
+namespace {
+
+struct Alloc {
+    char* base;
+    size_t off;
+    bool dry;
+    template <typename T>
+    T* take(size_t count)
+    {
+        const size_t o = off;
+        off = align_up(off + count * sizeof(T), kAlign);
+        return dry ? nullptr : reinterpret_cast<T*>(base + o);
+    }
+};
+
+clbm_status check_desc(const clbm_net_desc* d)
+{
+    if (!d) return CLBM_ERR_INVALID_ARG;
+    if (d->batch < 1 || d->cin < 1 || d->cin > 32 || d->cout < 1 || d->cout > 16)
+        return CLBM_ERR_INVALID_ARG;
+    if (d->height < 16 || d->width < 16 || d->height % 8 || d->width % 8) return CLBM_ERR_INVALID_ARG;
+    // the coarsest level must hold whole 64-pixel tiles
+    if (((long)d->batch * (d->height / 8) * (d->width / 8)) % 64 != 0) return CLBM_ERR_INVALID_ARG;
+    for (int k = 0; k < 4; ++k)
+        if (d->widths[k] < 32 || d->widths[k] % 32) return CLBM_ERR_INVALID_ARG;
+    return CLBM_OK;
+}
+
+// Lays out every buffer; with a.dry only counts bytes.
+void layout_net(clbm_net* n, Alloc& a)
+{
+    const clbm_net_desc& d = n->d;
+    const int B = d.batch, H = d.height, W = d.width;
+    const int w1 = d.widths[0], w2 = d.widths[1], w3 = d.widths[2], w4 = d.widths[3];
+    const size_t P1 = (size_t)B * H * W, P2 = P1 / 4, P3 = P1 / 16, P4 = P1 / 64;
+    const int cinp = round_up(d.cin, 32);
+    // activations
+    n->xin = a.take<bf16>(P1 * cinp);
+    n->a1 = a.take<bf16>(P1 * w1);
+    n->cat1 = a.take<bf16>(P1 * (w2 + w1));
+    n->p1 = a.take<bf16>(P2 * w1);
+    n->a2 = a.take<bf16>(P2 * w2);
+    n->cat2 = a.take<bf16>(P2 * (w3 + w2));
+    n->p2 = a.take<bf16>(P3 * w2);
+    n->a3 = a.take<bf16>(P3 * w3);
+    n->cat3 = a.take<bf16>(P3 * (w4 + w3));
+    n->p3 = a.take<bf16>(P4 * w3);
+    n->a4 = a.take<bf16>(P4 * w4);
+    n->m4 = a.take<bf16>(P4 * w4);
+    n->d3a = a.take<bf16>(P3 * w3);
+    n->d3b = a.take<bf16>(P3 * w3);
+    n->d2a = a.take<bf16>(P2 * w2);
+    n->d2b = a.take<bf16>(P2 * w2);
+    n->d1a = a.take<bf16>(P1 * w1);
+    n->d1b = a.take<bf16>(P1 * w1);
+    n->yout = a.take<float>(P1 * d.cout);
+    n->dyout = a.take<bf16>(P1 * 32);
+    // gradients
+    n->g_d1b = a.take<bf16>(P1 * w1);
+    n->g_d1a = a.take<bf16>(P1 * w1);
+    n->g_cat1 = a.take<bf16>(P1 * (w2 + w1));
+    n->g_d2b = a.take<bf16>(P2 * w2);
+    n->g_d2a = a.take<bf16>(P2 * w2);
+    n->g_cat2 = a.take<bf16>(P2 * (w3 + w2));
+    n->g_d3b = a.take<bf16>(P3 * w3);
+    n->g_d3a = a.take<bf16>(P3 * w3);
+    n->g_cat3 = a.take<bf16>(P3 * (w4 + w3));
+    n->g_m4 = a.take<bf16>(P4 * w4);
+    n->g_a4 = a.take<bf16>(P4 * w4);
+    n->g_p3 = a.take<bf16>(P4 * w3);
+    n->g_a3 = a.take<bf16>(P3 * w3);
+    n->g_p2 = a.take<bf16>(P3 * w2);
+    n->g_a2 = a.take<bf16>(P2 * w2);
+    n->g_p1 = a.take<bf16>(P2 * w1);
+    n->g_a1 = a.take<bf16>(P1 * w1);
+    const size_t zmax = std::max({P1 * (size_t)w1, P2 * (size_t)w2, P3 * (size_t)w3, P4 * (size_t)w4});
+    n->zscratch = zmax;
+    n->g_z = a.take<bf16>(zmax);
+
+    // layers
+    const int cin_[kLayers] = {d.cin, w1, w1, w2, w2, w3, w3, w4, w4 + w3, w3, w3 + w2, w2, w2 + w1, w1, w1};
+    const int cout_[kLayers] = {w1, w1, w2, w2, w3, w3, w4, w4, w3, w3, w2, w2, w1, w1, d.cout};
+    const int res_[kLayers] = {1, 1, 2, 2, 4, 4, 8, 8, 4, 4, 2, 2, 1, 1, 1};
+    size_t off = 0;
+    for (int k = 0; k < kLayers; ++k) {
+        Layer& l = n->L[k];
+        l.cin = cin_[k];
+        l.cout = cout_[k];
+        l.cin_pad = round_up(l.cin, 32);
+        l.nb = (l.cout % 64 == 0) ? 4 : (l.cout % 32 == 0 ? 2 : 1);
+        l.nout_pad = round_up(l.cout, 16 * l.nb);
+        l.cout_kpad = round_up(l.cout, 32);
+        l.H = H / res_[k];
+        l.W = W / res_[k];
+        l.woff = off;
+        off += (size_t)l.cout * l.cin * 9;
+        l.boff = off;
+        off += l.cout;
+        l.wf = a.take<bf16>((size_t)l.nout_pad * 9 * l.cin_pad);
+        l.wb = k == 0 ? nullptr : a.take<bf16>((size_t)l.cin_pad * 9 * l.cout_kpad);
+    }
+    n->nparams = off;
+    n->params = a.take<float>(off);
+    n->grads = a.take<float>(off);
+    n->adam_m = a.take<float>(off);
+    n->adam_v = a.take<float>(off);
+    // split-K partials: pixels per split fixed at 4096
+    size_t wp = 0;
+    for (int k = 0; k < kLayers; ++k) {
+        const Layer& l = n->L[k];
+        const size_t P = (size_t)B * l.H * l.W;
+        const size_t splits = (P + 4095) / 4096;
+        wp = std::max(wp, splits * round_up(l.cout, 16) * 9 * l.cin_pad);
+    }
+    n->wpart_floats = wp;
+    n->wpart = a.take<float>(wp);
+    n->bpart = a.take<float>((P1 + 4095) / 4096 * std::max({w1, w2, w3, w4, d.cout}));
+    n->lpart = a.take<double>((P1 * 32 + 255) / 256);
+    n->loss = a.take<double>(1);
+
+    // views: forward input/output of each layer
+    auto V = [](bf16* p, int C, int off) { return TView{p, C, off}; };
+    Layer* L = n->L;
+    L[0].in = V(n->xin, cinp, 0);      L[0].out = V(n->a1, w1, 0);
+    L[1].in = V(n->a1, w1, 0);         L[1].out = V(n->cat1, w2 + w1, w2);   // s1
+    L[2].in = V(n->p1, w1, 0);         L[2].out = V(n->a2, w2, 0);
+    L[3].in = V(n->a2, w2, 0);         L[3].out = V(n->cat2, w3 + w2, w3);   // s2
+    L[4].in = V(n->p2, w2, 0);         L[4].out = V(n->a3, w3, 0);
+    L[5].in = V(n->a3, w3, 0);         L[5].out = V(n->cat3, w4 + w3, w4);   // s3
+    L[6].in = V(n->p3, w3, 0);         L[6].out = V(n->a4, w4, 0);
+    L[7].in = V(n->a4, w4, 0);         L[7].out = V(n->m4, w4, 0);
+    L[8].in = V(n->cat3, w4 + w3, 0);  L[8].out = V(n->d3a, w3, 0);
+    L[9].in = V(n->d3a, w3, 0);        L[9].out = V(n->d3b, w3, 0);
+    L[10].in = V(n->cat2, w3 + w2, 0); L[10].out = V(n->d2a, w2, 0);
+    L[11].in = V(n->d2a, w2, 0);       L[11].out = V(n->d2b, w2, 0);
+    L[12].in = V(n->cat1, w2 + w1, 0); L[12].out = V(n->d1a, w1, 0);
+    L[13].in = V(n->d1a, w1, 0);       L[13].out = V(n->d1b, w1, 0);
+    L[14].in = V(n->d1b, w1, 0);       L[14].out = V(nullptr, 0, 0);
+    // gradient w.r.t. each layer's input
+    L[0].din = V(nullptr, 0, 0);
+    L[1].din = V(n->g_a1, w1, 0);
+    L[2].din = V(n->g_p1, w1, 0);
+    L[3].din = V(n->g_a2, w2, 0);
+    L[4].din = V(n->g_p2, w2, 0);
+    L[5].din = V(n->g_a3, w3, 0);
+    L[6].din = V(n->g_p3, w3, 0);
+    L[7].din = V(n->g_a4, w4, 0);
+    L[8].din = V(n->g_cat3, w4 + w3, 0);
+    L[9].din = V(n->g_d3a, w3, 0);
+    L[10].din = V(n->g_cat2, w3 + w2, 0);
+    L[11].din = V(n->g_d2a, w2, 0);
+    L[12].din = V(n->g_cat1, w2 + w1, 0);
+    L[13].din = V(n->g_d1a, w1, 0);
+    L[14].din = V(n->g_d1b, w1, 0);
+}
+
+dim3 grid1(size_t n, int block = 256) { return dim3((unsigned)((n + block - 1) / block)); }
+
+clbm_status conv_launch(clbm_net* n, const Layer& l, TView in, int cin_pad, const bf16* w,
+                        const float* bias, int N, int nb, int npad, int mode, TView out, float* yf)
+{
+    const int P = n->d.batch * l.H * l.W;
+    const dim3 grid(P / 64, npad / (16 * nb));
+    const void* fn = nb == 4 ? reinterpret_cast<const void*>(&k_conv<4>)
+                   : nb == 2 ? reinterpret_cast<const void*>(&k_conv<2>)
+                             : reinterpret_cast<const void*>(&k_conv<1>);
+    int xC = in.C, xoff = in.off, Cin = cin_pad, H = l.H, W = l.W, yC = out.C, yoff = out.off;
+    const bf16* x = in.p;
+    bf16* y = out.p;
+    void* args[] = {&x, &xC, &xoff, &Cin, (void*)&w, (void*)&bias, &N, &H, &W, &mode, &y, &yC, &yoff, &yf};
+    CLBM_HIP(hipLaunchKernel(fn, grid, dim3(256), args, 0, n->stream));
+    return CLBM_OK;
+}
+
+clbm_status prep_weights(clbm_net* n)
+{
+    for (int k = 0; k < kLayers; ++k) {
+        const Layer& l = n->L[k];
+        const size_t nf = (size_t)l.nout_pad * 9 * l.cin_pad;
+        const size_t nbk = l.wb ? (size_t)l.cin_pad * 9 * l.cout_kpad : 0;
+        hipLaunchKernelGGL(k_weight_prep, grid1(std::max(nf, nbk)), dim3(256), 0, n->stream,
+                           n->params + l.woff, l.cout, l.cin, l.nout_pad, l.cin_pad, l.cout_kpad,
+                           l.wf, l.wb);
+        CLBM_HIP(hipGetLastError());
+    }
+    n->weights_stale = 0;
+    return CLBM_OK;
+}
+
+clbm_status ew_launch_check() { CLBM_HIP(hipGetLastError()); return CLBM_OK; }
+
+clbm_status pool(clbm_net* n, TView x, int C, int H, int W, TView y)
+{
+    const int B = n->d.batch;
+    hipLaunchKernelGGL(k_avgpool, grid1((size_t)B * (H / 2) * (W / 2) * C), dim3(256), 0, n->stream,
+                       x.p, x.C, x.off, C, H, W, B, y.p, y.C, y.off);
+    return ew_launch_check();
+}
+
+clbm_status upsample(clbm_net* n, TView x, int C, int H, int W, TView y)
+{
+    const int B = n->d.batch;
+    hipLaunchKernelGGL(k_upsample, grid1((size_t)B * 4 * H * W * C), dim3(256), 0, n->stream, x.p,
+                       x.C, x.off, C, H, W, B, y.p, y.C, y.off);
+    return ew_launch_check();
+}
+
+// Backward through one convolution: dz (gradient w.r.t. its output pre-activation,
+// ReLU already applied) -> weight and bias gradients, and the input gradient when the
+// layer has one.
+clbm_status conv_backward(clbm_net* n, int k, TView dz)
+{
+    const Layer& l = n->L[k];
+    const int B = n->d.batch;
+    const int P = B * l.H * l.W;
+    const int pps = 4096;
+    const int splits = (P + pps - 1) / pps;
+    const int cout16 = round_up(l.cout, 16);
+    // weight gradient
+    hipLaunchKernelGGL(k_wgrad, dim3((cout16 / 16) * (l.cin_pad / 16), 9, splits), dim3(64), 0,
+                       n->stream, dz.p, dz.C, cout16, l.in.p, l.in.C, l.in.off, l.cin_pad, l.H, l.W,
+                       P, pps, n->wpart);
+    CLBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_wgrad_reduce, grid1((size_t)l.cout * 9 * l.cin), dim3(256), 0, n->stream,
+                       n->wpart, splits, cout16, l.cin_pad, l.cout, l.cin, n->grads + l.woff);
+    CLBM_HIP(hipGetLastError());
+    // bias gradient
+    hipLaunchKernelGGL(k_bias_grad, dim3((l.cout + 63) / 64, splits), dim3(64, 4), 0, n->stream, dz.p,
+                       dz.C, l.cout, P, pps, n->bpart);
+    CLBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_bias_reduce, grid1(l.cout), dim3(256), 0, n->stream, n->bpart, splits, l.cout,
+                       n->grads + l.boff);
+    CLBM_HIP(hipGetLastError());
+    // input gradient: convolution of dz with the flipped, transposed kernel
+    if (l.din.p) {
+        const int nb = (l.cin % 64 == 0) ? 4 : 2;
+        return conv_launch(n, l, dz, l.cout_kpad, l.wb, nullptr, l.cin, nb, round_up(l.cin, 16 * nb), 1,
+                           l.din, nullptr);
+    }
+    return CLBM_OK;
+}
+
+clbm_status relu_grad(clbm_net* n, TView dy, TView dpool_parent, TView act, int C, int H, int W, TView dz)
+{
+    const int B = n->d.batch;
+    hipLaunchKernelGGL(k_relu_grad, grid1((size_t)B * H * W * C), dim3(256), 0, n->stream, dy.p, dy.C,
+                       dy.off, dpool_parent.p, dpool_parent.C, act.p, act.C, act.off, C, H, W, B,
+                       dz.p, dz.C);
+    return ew_launch_check();
+}
+
+}  // namespace
+
+extern "C" {
+
+clbm_status clbm_net_param_count(const clbm_net_desc* d, size_t* count)
+{
+    if (!count) return CLBM_ERR_INVALID_ARG;
+    clbm_status st = check_desc(d);
+    if (st != CLBM_OK) return st;
+    clbm_net tmp;
+    std::memset(&tmp, 0, sizeof tmp);
+    tmp.d = *d;
+    Alloc a{nullptr, 0, true};
+    layout_net(&tmp, a);
+    *count = tmp.nparams;
+    return CLBM_OK;
+}
+
+clbm_status clbm_net_workspace_bytes(const clbm_net_desc* d, size_t* bytes)
+{
+    if (!bytes) return CLBM_ERR_INVALID_ARG;
+    clbm_status st = check_desc(d);
+    if (st != CLBM_OK) return st;
+    clbm_net tmp;
+    std::memset(&tmp, 0, sizeof tmp);
+    tmp.d = *d;
+    Alloc a{nullptr, 0, true};
+    layout_net(&tmp, a);
+    *bytes = a.off;
+    return CLBM_OK;
+}
+
+clbm_status clbm_net_create(const clbm_net_desc* d, void* d_workspace, size_t bytes, void* hip_stream,
+                            clbm_net** out)
+{
+    if (!out) return CLBM_ERR_INVALID_ARG;
+    *out = nullptr;
+    clbm_status st = check_desc(d);
+    if (st != CLBM_OK) return st;
+    size_t need = 0;
+    clbm_net_workspace_bytes(d, &need);
+    if (!d_workspace || ((uintptr_t)d_workspace) % kAlign) return CLBM_ERR_INVALID_ARG;
+    if (bytes < need) return CLBM_ERR_BUFFER_TOO_SMALL;
+    clbm_net* n = new (std::nothrow) clbm_net;
+    if (!n) return CLBM_ERR_INVALID_ARG;
+    std::memset(n, 0, sizeof *n);
+    n->d = *d;
+    n->stream = (hipStream_t)hip_stream;
+    Alloc a{(char*)d_workspace, 0, false};
+    layout_net(n, a);
+    // zero everything once (padding channels must read as zeros), Adam moments included
+    hipError_t e = hipMemsetAsync(d_workspace, 0, need, n->stream);
+    if (e != hipSuccess) {
+        delete n;
+        set_last_hip_error(e, "hipMemsetAsync", __FILE__, __LINE__);
+        return CLBM_ERR_HIP;
+    }
+    n->weights_stale = 1;
+    *out = n;
+    return CLBM_OK;
+}
+
+void clbm_net_destroy(clbm_net* n) { delete n; }
+
+clbm_status clbm_net_set_params(clbm_net* n, const float* d_params)
+{
+    if (!n || !d_params) return CLBM_ERR_INVALID_ARG;
+    CLBM_HIP(hipMemcpyAsync(n->params, d_params, n->nparams * sizeof(float), hipMemcpyDeviceToDevice,
+                            n->stream));
+    n->weights_stale = 1;
+    return CLBM_OK;
+}
+
+clbm_status clbm_net_get_params(clbm_net* n, float* d_params)
+{
+    if (!n || !d_params) return CLBM_ERR_INVALID_ARG;
+    CLBM_HIP(hipMemcpyAsync(d_params, n->params, n->nparams * sizeof(float), hipMemcpyDeviceToDevice,
+                            n->stream));
+    return CLBM_OK;
+}
+
+clbm_status clbm_net_get_grads(clbm_net* n, float* d_grads)
+{
+    if (!n || !d_grads) return CLBM_ERR_INVALID_ARG;
+    CLBM_HIP(hipMemcpyAsync(d_grads, n->grads, n->nparams * sizeof(float), hipMemcpyDeviceToDevice,
+                            n->stream));
+    return CLBM_OK;
+}
+
+clbm_status clbm_net_forward(clbm_net* n, const float* d_x, float* d_y)
+{
+    if (!n || !d_x) return CLBM_ERR_INVALID_ARG;
+    const clbm_net_desc& d = n->d;
+    const int B = d.batch, H = d.height, W = d.width;
+    const int w1 = d.widths[0], w2 = d.widths[1], w3 = d.widths[2], w4 = d.widths[3];
+    clbm_status st = CLBM_OK;
+    if (n->weights_stale && (st = prep_weights(n)) != CLBM_OK) return st;
+    const int cinp = round_up(d.cin, 32);
+    hipLaunchKernelGGL(k_pack_input, grid1((size_t)B * H * W * cinp), dim3(256), 0, n->stream, d_x, d.cin,
+                       H * W, B * H * W, n->xin, cinp);
+    CLBM_HIP(hipGetLastError());
+    Layer* L = n->L;
+    auto fwd = [&](int k) {
+        const Layer& l = L[k];
+        return conv_launch(n, l, l.in, l.cin_pad, l.wf, n->params + l.boff, l.cout, l.nb, l.nout_pad,
+                           k == 14 ? 2 : 0, l.out, k == 14 ? n->yout : nullptr);
+    };
+    auto V = [](bf16* p, int C, int off) { return TView{p, C, off}; };
+    if ((st = fwd(0)) || (st = fwd(1))) return st;
+    if ((st = pool(n, V(n->cat1, w2 + w1, w2), w1, H, W, V(n->p1, w1, 0)))) return st;
+    if ((st = fwd(2)) || (st = fwd(3))) return st;
+    if ((st = pool(n, V(n->cat2, w3 + w2, w3), w2, H / 2, W / 2, V(n->p2, w2, 0)))) return st;
+    if ((st = fwd(4)) || (st = fwd(5))) return st;
+    if ((st = pool(n, V(n->cat3, w4 + w3, w4), w3, H / 4, W / 4, V(n->p3, w3, 0)))) return st;
+    if ((st = fwd(6)) || (st = fwd(7))) return st;
+    if ((st = upsample(n, V(n->m4, w4, 0), w4, H / 8, W / 8, V(n->cat3, w4 + w3, 0)))) return st;
+    if ((st = fwd(8)) || (st = fwd(9))) return st;
+    if ((st = upsample(n, V(n->d3b, w3, 0), w3, H / 4, W / 4, V(n->cat2, w3 + w2, 0)))) return st;
+    if ((st = fwd(10)) || (st = fwd(11))) return st;
+    if ((st = upsample(n, V(n->d2b, w2, 0), w2, H / 2, W / 2, V(n->cat1, w2 + w1, 0)))) return st;
+    if ((st = fwd(12)) || (st = fwd(13)) || (st = fwd(14))) return st;
+    if (d_y)
+        CLBM_HIP(hipMemcpyAsync(d_y, n->yout, (size_t)B * d.cout * H * W * sizeof(float),
+                                hipMemcpyDeviceToDevice, n->stream));
+    return CLBM_OK;
+}
+
+clbm_status clbm_net_backward(clbm_net* n, const float* d_target, double* loss)
+{
+    if (!n || !d_target) return CLBM_ERR_INVALID_ARG;
+    const clbm_net_desc& d = n->d;
+    const int B = d.batch, H = d.height, W = d.width;
+    const int w1 = d.widths[0], w2 = d.widths[1], w3 = d.widths[2], w4 = d.widths[3];
+    const int P1 = B * H * W;
+    auto V = [](bf16* p, int C, int off) { return TView{p, C, off}; };
+    const TView none = V(nullptr, 0, 0);
+    clbm_status st = CLBM_OK;
+    // loss and its gradient
+    const int nblk = (P1 * 32 + 255) / 256;
+    hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(256), 0, n->stream, n->yout, d_target, d.cout, H * W, P1,
+                       32, 1.0 / ((double)P1 * d.cout), n->dyout, n->lpart);
+    CLBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_d, dim3(1), dim3(256), 0, n->stream, n->lpart, nblk, n->loss);
+    CLBM_HIP(hipGetLastError());
+    auto zv = [&](int C) { return TView{n->g_z, C, 0}; };
+    // output layer (no activation)
+    if ((st = conv_backward(n, 14, V(n->dyout, 32, 0)))) return st;
+    // level-1 decoder
+    if ((st = relu_grad(n, V(n->g_d1b, w1, 0), none, V(n->d1b, w1, 0), w1, H, W, zv(w1)))) return st;
+    if ((st = conv_backward(n, 13, zv(w1)))) return st;
+    if ((st = relu_grad(n, V(n->g_d1a, w1, 0), none, V(n->d1a, w1, 0), w1, H, W, zv(w1)))) return st;
+    if ((st = conv_backward(n, 12, zv(w1)))) return st;
+    // g_cat1 = [d up(d2b) | d s1]
+    hipLaunchKernelGGL(k_upsample_bwd, grid1((size_t)B * (H / 2) * (W / 2) * w2), dim3(256), 0, n->stream,
+                       n->g_cat1, w2 + w1, 0, w2, H / 2, W / 2, B, n->g_d2b, w2, 0);
+    CLBM_HIP(hipGetLastError());
+    // level-2 decoder
+    if ((st = relu_grad(n, V(n->g_d2b, w2, 0), none, V(n->d2b, w2, 0), w2, H / 2, W / 2, zv(w2)))) return st;
+    if ((st = conv_backward(n, 11, zv(w2)))) return st;
+    if ((st = relu_grad(n, V(n->g_d2a, w2, 0), none, V(n->d2a, w2, 0), w2, H / 2, W / 2, zv(w2)))) return st;
+    if ((st = conv_backward(n, 10, zv(w2)))) return st;
+    hipLaunchKernelGGL(k_upsample_bwd, grid1((size_t)B * (H / 4) * (W / 4) * w3), dim3(256), 0, n->stream,
+                       n->g_cat2, w3 + w2, 0, w3, H / 4, W / 4, B, n->g_d3b, w3, 0);
+    CLBM_HIP(hipGetLastError());
+    // level-3 decoder
+    if ((st = relu_grad(n, V(n->g_d3b, w3, 0), none, V(n->d3b, w3, 0), w3, H / 4, W / 4, zv(w3)))) return st;
+    if ((st = conv_backward(n, 9, zv(w3)))) return st;
+    if ((st = relu_grad(n, V(n->g_d3a, w3, 0), none, V(n->d3a, w3, 0), w3, H / 4, W / 4, zv(w3)))) return st;
+    if ((st = conv_backward(n, 8, zv(w3)))) return st;
+    hipLaunchKernelGGL(k_upsample_bwd, grid1((size_t)B * (H / 8) * (W / 8) * w4), dim3(256), 0, n->stream,
+                       n->g_cat3, w4 + w3, 0, w4, H / 8, W / 8, B, n->g_m4, w4, 0);
+    CLBM_HIP(hipGetLastError());
+    // bottom level
+    if ((st = relu_grad(n, V(n->g_m4, w4, 0), none, V(n->m4, w4, 0), w4, H / 8, W / 8, zv(w4)))) return st;
+    if ((st = conv_backward(n, 7, zv(w4)))) return st;
+    if ((st = relu_grad(n, V(n->g_a4, w4, 0), none, V(n->a4, w4, 0), w4, H / 8, W / 8, zv(w4)))) return st;
+    if ((st = conv_backward(n, 6, zv(w4)))) return st;
+    // encoder: skip gradient + pooled gradient, through the ReLU
+    if ((st = relu_grad(n, V(n->g_cat3, w4 + w3, w4), V(n->g_p3, w3, 0), V(n->cat3, w4 + w3, w4), w3,
+                        H / 4, W / 4, zv(w3)))) return st;
+    if ((st = conv_backward(n, 5, zv(w3)))) return st;
+    if ((st = relu_grad(n, V(n->g_a3, w3, 0), none, V(n->a3, w3, 0), w3, H / 4, W / 4, zv(w3)))) return st;
+    if ((st = conv_backward(n, 4, zv(w3)))) return st;
+    if ((st = relu_grad(n, V(n->g_cat2, w3 + w2, w3), V(n->g_p2, w2, 0), V(n->cat2, w3 + w2, w3), w2,
+                        H / 2, W / 2, zv(w2)))) return st;
+    if ((st = conv_backward(n, 3, zv(w2)))) return st;
+    if ((st = relu_grad(n, V(n->g_a2, w2, 0), none, V(n->a2, w2, 0), w2, H / 2, W / 2, zv(w2)))) return st;
+    if ((st = conv_backward(n, 2, zv(w2)))) return st;
+    if ((st = relu_grad(n, V(n->g_cat1, w2 + w1, w2), V(n->g_p1, w1, 0), V(n->cat1, w2 + w1, w2), w1, H,
+                        W, zv(w1)))) return st;
+    if ((st = conv_backward(n, 1, zv(w1)))) return st;
+    if ((st = relu_grad(n, V(n->g_a1, w1, 0), none, V(n->a1, w1, 0), w1, H, W, zv(w1)))) return st;
+    if ((st = conv_backward(n, 0, zv(w1)))) return st;
+    if (loss) {
+        double sum = 0.0;
+        CLBM_HIP(hipMemcpyAsync(&sum, n->loss, sizeof(double), hipMemcpyDeviceToHost, n->stream));
+        CLBM_HIP(hipStreamSynchronize(n->stream));
+        *loss = sum / ((double)P1 * d.cout);
+    }
+    return CLBM_OK;
+}
+
+clbm_status clbm_net_adam(clbm_net* n, float lr, float beta1, float beta2, float eps, int t)
+{
+    if (!n || t < 1) return CLBM_ERR_INVALID_ARG;
+    const float c1 = 1.f - std::pow(beta1, (float)t), c2 = 1.f - std::pow(beta2, (float)t);
+    hipLaunchKernelGGL(k_adam, grid1(n->nparams), dim3(256), 0, n->stream, n->params, n->grads, n->adam_m,
+                       n->adam_v, n->nparams, lr, beta1, beta2, eps, c1, c2);
+    CLBM_HIP(hipGetLastError());
+    n->weights_stale = 1;
+    return CLBM_OK;
+}
+
+clbm_status clbm_resample_bilinear(const float* d_src, int sh, int sw, float* d_dst, int dh, int dw,
+                                   int nfields, const float* scale, const float* shift,
+                                   void* hip_stream)
+{
+    if (!d_src || !d_dst || sh < 1 || sw < 1 || dh < 1 || dw < 1 || nfields < 1 || nfields > 16)
+        return CLBM_ERR_INVALID_ARG;
+    FieldAffine af;
+    for (int f = 0; f < 16; ++f) {
+        af.scale[f] = (scale && f < nfields) ? scale[f] : 1.f;
+        af.shift[f] = (shift && f < nfields) ? shift[f] : 0.f;
+    }
+    hipLaunchKernelGGL(k_resample, grid1((size_t)nfields * dh * dw), dim3(256), 0, (hipStream_t)hip_stream,
+                       d_src, sh, sw, d_dst, dh, dw, nfields, af);
+    CLBM_HIP(hipGetLastError());
+    return CLBM_OK;
+}
+
+clbm_status clbm_net_features(const clbm_problem_code* d_codes, int batch, int height, int width,
+                              float* d_out, void* hip_stream)
+{
+    if (!d_codes || !d_out || batch < 1 || height < 1 || width < 1) return CLBM_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_features, grid1((size_t)batch * height * width), dim3(256), 0,
+                       (hipStream_t)hip_stream, d_codes, batch, height, width, d_out);
+    CLBM_HIP(hipGetLastError());
+    return CLBM_OK;
+}
+
+clbm_status clbm_problem_encode(const clbm_params* p, clbm_problem_code* out)
+{
+    if (!p || !out) return CLBM_ERR_INVALID_ARG;
+    Rates r;
+    clbm_status st = derive_rates(p, &r);
+    if (st != CLBM_OK) return st;
+    // Sec. 3.3: the cavity height H = ny, dT = T(x-) - T(x+) of the Dirichlet side walls
+    // (1 when they are not both Dirichlet); Ra = g beta dT H^3/(nu alpha), Pr = nu/alpha.
+    const double H = p->ny;
+    double dT = 1.0;
+    if (p->side[0].kind == CLBM_WALL && p->side[1].kind == CLBM_WALL && p->side[0].b1 == 0.0 &&
+        p->side[1].b1 == 0.0 && p->side[0].b2 != 0.0 && p->side[1].b2 != 0.0) {
+        const double d = p->side[0].b3 / p->side[0].b2 - p->side[1].b3 / p->side[1].b2;
+        if (d != 0.0) dT = std::fabs(d);
+    }
+    const double Ra = std::max(p->g_beta * dT * H * H * H / (p->nu * p->alpha), 1.0);
+    std::memset(out, 0, sizeof *out);
+    out->log10_ra = (float)std::log10(Ra);
+    out->pr = (float)(p->nu / p->alpha);
+    out->q_star = (float)(p->Q * H * H / (p->alpha * dT));
+    out->log2_aspect = (float)std::log2((double)p->nx / p->ny);
+    for (int s = 0; s < 4; ++s) {
+        const clbm_side& sd = p->side[s];
+        if (sd.kind != CLBM_WALL) {
+            out->kind[s] = 0;
+        } else if (sd.b1 == 0.0) {
+            out->kind[s] = 1;
+            out->theta_wall[s] = (float)((sd.b3 / sd.b2 - p->T0) / dT);
+        } else {
+            out->kind[s] = (sd.b2 == 0.0 && sd.b3 == 0.0) ? 2 : 3;
+        }
+    }
+    out->u_scale = (float)std::sqrt(p->g_beta * dT * H);
+    out->t_scale = (float)dT;
+    return CLBM_OK;
+}
+
+}  // extern "C"

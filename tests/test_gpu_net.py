@@ -1,0 +1,141 @@
+"""Warm-start network kernels (BF16 MFMA, FP32 accumulation) against the FP64 reference
+network of oracle/net.py, through the C ABI.
+
+Tolerances follow from BF16: operands carry 8 significant bits (relative rounding
+2^-9 ~ 2e-3 per element); through 15 layers of 3x3 convolutions with FP32 accumulation
+the outputs agree to a relative L2 error of 2e-2, and every parameter gradient tensor
+to 5e-2 (gradients pass through the BF16 activations twice).
+"""
+import numpy as np
+import pytest
+
+from oracle import net as ref
+
+pytestmark = pytest.mark.gpu
+
+CIN, COUT, WIDTHS = 8, 3, (32, 64, 128, 256)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    import torch
+    import paper_1801_04577_amd as clbm
+    assert torch.cuda.is_available()
+    clbm.ensure_built()
+
+
+def flatten(params):
+    return np.concatenate([np.concatenate([w.reshape(-1), b]) for w, b in params])
+
+
+def unflatten(vec, like):
+    out, k = [], 0
+    for w, b in like:
+        nw, nb = w.size, b.size
+        out.append((vec[k:k + nw].reshape(w.shape), vec[k + nw:k + nw + nb]))
+        k += nw + nb
+    assert k == vec.size
+    return out
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def setup(batch=4, H=32, seed=0):
+    rng = np.random.default_rng(seed)
+    params = ref.init_params(CIN, COUT, WIDTHS, seed=seed + 1)
+    params = [(w.astype(np.float32).astype(np.float64),
+               rng.normal(scale=0.05, size=b.shape).astype(np.float32).astype(np.float64))
+              for w, b in params]
+    xs = rng.normal(size=(batch, CIN, H, H)).astype(np.float32).astype(np.float64)
+    ts = rng.normal(scale=0.5, size=(batch, COUT, H, H)).astype(np.float32).astype(np.float64)
+    return params, xs, ts
+
+
+def gpu_net(batch, H):
+    import paper_1801_04577_amd as clbm
+    return clbm.Net(batch, H, H, CIN, COUT, WIDTHS)
+
+
+def test_param_count():
+    import paper_1801_04577_amd as clbm
+    params, _, _ = setup()
+    n = gpu_net(4, 32)
+    assert n.nparams == flatten(params).size
+
+
+def test_forward_matches_reference():
+    import torch
+    params, xs, ts = setup()
+    n = gpu_net(4, 32)
+    n.set_params(torch.from_numpy(flatten(params).astype(np.float32)))
+    y = n.forward(torch.from_numpy(xs.astype(np.float32))).cpu().numpy().astype(np.float64)
+    want = np.stack([ref.forward(params, x) for x in xs])
+    e = rel(y, want)
+    print("forward rel L2 %.3e" % e, flush=True)
+    assert e < 2e-2
+
+
+def test_gradients_match_reference():
+    import torch
+    params, xs, ts = setup(seed=3)
+    n = gpu_net(4, 32)
+    n.set_params(torch.from_numpy(flatten(params).astype(np.float32)))
+    n.forward(torch.from_numpy(xs.astype(np.float32)))
+    loss = n.backward(torch.from_numpy(ts.astype(np.float32)))
+    want_loss, want = ref.loss_and_grads(params, xs, ts)
+    assert loss == pytest.approx(want_loss, rel=2e-2)
+    got = unflatten(n.grads().cpu().numpy().astype(np.float64), params)
+    worst = 0.0
+    for k, ((gw, gb), (ww, wb)) in enumerate(zip(got, want)):
+        ew, eb = rel(gw, ww), rel(gb, wb)
+        print("layer %2d  dW %.3e  db %.3e" % (k, ew, eb), flush=True)
+        worst = max(worst, ew, eb)
+    assert worst < 5e-2
+
+
+def test_training_reduces_loss():
+    import torch
+    params, xs, ts = setup(seed=5)
+    # a learnable target: the reference network's own output for other weights
+    teacher = ref.init_params(CIN, COUT, WIDTHS, seed=99)
+    ts = np.stack([ref.forward(teacher, x) for x in xs]).astype(np.float32)
+    n = gpu_net(4, 32)
+    n.set_params(torch.from_numpy(flatten(params).astype(np.float32)))
+    x = torch.from_numpy(xs.astype(np.float32)).cuda()
+    t = torch.from_numpy(ts).cuda()
+    losses = []
+    for step in range(1, 151):
+        n.forward(x)
+        losses.append(n.backward(t))
+        n.adam(1e-3, step)
+    print("loss %.4e -> %.4e" % (losses[0], losses[-1]), flush=True)
+    assert losses[-1] < 0.2 * losses[0]
+
+
+def test_resample_bilinear():
+    import torch
+    import paper_1801_04577_amd as clbm
+    rng = np.random.default_rng(0)
+    src = rng.normal(size=(2, 6, 10)).astype(np.float32)
+    out = clbm.resample(torch.from_numpy(src).cuda(), 9, 4).cpu().numpy()
+
+    def bilinear(f, dh, dw):
+        sh, sw = f.shape
+        res = np.zeros((dh, dw))
+        for y in range(dh):
+            for x in range(dw):
+                fy = min(max((y + 0.5) * sh / dh - 0.5, 0.0), sh - 1)
+                fx = min(max((x + 0.5) * sw / dw - 0.5, 0.0), sw - 1)
+                y0, x0 = int(fy), int(fx)
+                y1, x1 = min(y0 + 1, sh - 1), min(x0 + 1, sw - 1)
+                ty, tx = fy - y0, fx - x0
+                res[y, x] = ((1 - ty) * ((1 - tx) * f[y0, x0] + tx * f[y0, x1])
+                             + ty * ((1 - tx) * f[y1, x0] + tx * f[y1, x1]))
+        return res
+
+    for k in range(2):
+        np.testing.assert_allclose(out[k], bilinear(src[k].astype(np.float64), 9, 4), atol=1e-6)
+    same = clbm.resample(torch.from_numpy(src).cuda(), 6, 10).cpu().numpy()
+    np.testing.assert_array_equal(same, src)

@@ -155,3 +155,38 @@ def sweep(count=256, seed=2024, sides=SWEEP_SIDES, ra_range=(1e3, 1e6), pr_range
         prob["meta"] = {"Ra": Ra, "Pr": Pr, "U": Uk}
         out.append((prob, int(seed * 1000 + k)))
     return out
+
+
+# --------------------------------------------------------------------------
+# Warm-start sets: cavities described by (Ra, Pr, Q*) with Q* = Q H^2/(alpha dT)
+# --------------------------------------------------------------------------
+
+def warmstart_problems(count, seed, sides=(64,), square=True, ra_range=(1e3, 1e6),
+                       pr_range=(0.7, 7.0), qstar_range=(0.0, 4.0), U=0.1, tau_max=2.0):
+    """Seeded cavities for the learned warm start: Ra log-uniform, Pr uniform, the
+    source given through Q* uniform (so that the internal heating stays comparable to
+    the wall-driven flow at every size), sides drawn from `sides` (square or a <= b <= 2a),
+    the velocity scale lowered where U would give tau_nu > tau_max. Returns a list of
+    (problem, noise_seed)."""
+    u = uniform01(seed, count * 8).reshape(count, 8)
+    out = []
+    for k in range(count):
+        if square:
+            nx = ny = int(sides[min(int(u[k, 0] * len(sides)), len(sides) - 1)])
+        else:
+            pairs = [(a, b) for a in sides for b in sides if a <= b <= 2 * a]
+            a, b = pairs[min(int(u[k, 0] * len(pairs)), len(pairs) - 1)]
+            nx, ny = (a, b) if u[k, 1] < 0.5 else (b, a)
+        Ra = 10.0 ** (math.log10(ra_range[0]) + u[k, 2] * (math.log10(ra_range[1]) - math.log10(ra_range[0])))
+        Pr = pr_range[0] + u[k, 3] * (pr_range[1] - pr_range[0])
+        qs = qstar_range[0] + u[k, 4] * (qstar_range[1] - qstar_range[0])
+        Uk = U
+        nu = Uk * ny * math.sqrt(Pr / Ra)
+        nu_max = (tau_max - 0.5) / 3.0
+        if nu > nu_max:
+            Uk = U * nu_max / nu
+        nu, alpha, _ = cavity_params(ny, Ra, Pr, Uk, 1.0)
+        prob = cavity(nx, ny, Ra=Ra, Pr=Pr, Q=qs * alpha / (ny * ny), U=Uk)
+        prob["meta"] = {"Ra": Ra, "Pr": Pr, "Qstar": qs, "U": Uk}
+        out.append((prob, int(seed * 1000 + k)))
+    return out
