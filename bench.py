@@ -204,6 +204,200 @@ def summarize_profiles(trace_db, fetch_db, write_db, precision, n, command):
     print(json.dumps({"written": tag, "traffic_over_algorithmic": traffic / alg}))
 
 
+def batched_sweep(args):
+    """The batched form on the 256-cavity sweep: autotuned one-launch-per-step over a
+    device tile list, against a loop of per-cavity launches of the single-lattice step on
+    the same cavities; then a run of every cavity to its residual 1e-7 with on-device
+    retirement (graph of K steps + convergence check + tile-list compaction)."""
+    import numpy as np
+    import torch
+    import paper_1801_04577_amd as clbm
+    import workloads as W
+
+    sets = W.sweep(count=args.sweep_count, seed=2024)
+    probs = [p for p, _ in sets]
+    nodes = sum(p["nx"] * p["ny"] for p in probs)
+    inits = [{"T": torch.from_numpy((p["T0"] + W.noise_field(sd, p["nx"], p["ny"], 1e-4)).astype(np.float32))}
+             for p, sd in sets]
+    log("batched: %d cavities, %d nodes" % (len(probs), nodes))
+    b = clbm.Batch(probs)
+    cache = args.write_cache or None
+    if cache and os.path.exists(cache):
+        os.remove(cache)
+    best = b.autotune(steps=20, cache_path=cache)
+    log("batched: autotuned tile %s" % best)
+    for i, f in enumerate(inits):
+        b.init(i, **f)
+    torch.cuda.synchronize()
+    b.step(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(args.sweep_steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    mlups_batch = nodes * args.sweep_steps / t_batch / 1e6
+    log("batched: %.1f MLUPS (one launch per step)" % mlups_batch)
+    # the same cavities advanced one launch per cavity per step
+    solvers = []
+    for p, f in zip(probs, inits):
+        sv = clbm.Solver(p)
+        sv.init(**f)
+        solvers.append(sv)
+    for sv in solvers:
+        sv.step(2)
+    torch.cuda.synchronize()
+    loop_steps = max(2, args.sweep_steps // 10)
+    t0 = time.perf_counter()
+    for _ in range(loop_steps):
+        for sv in solvers:
+            sv.step(1)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    mlups_loop = nodes * loop_steps / t_loop / 1e6
+    log("batched: loop of per-cavity launches %.1f MLUPS" % mlups_loop)
+    del solvers
+    # run to convergence from the seeded initial state
+    for i, f in enumerate(inits):
+        b.init(i, **f)
+    t0 = time.perf_counter()
+    steps, status = b.run(max_steps=args.sweep_max_steps, tol=1e-7, K=1000)
+    t_run = time.perf_counter() - t0
+    lups = sum(st * p["nx"] * p["ny"] for st, p in zip(steps, probs))
+    counts = {k: status.count(k) for k in set(status)}
+    log("batched: run to 1e-7: %s in %.1f s, %.1f MLUPS" % (counts, t_run, lups / t_run / 1e6))
+    return {"workload": "%d cavities (sides 64-512, a<=b<=2a; Ra 1e3-1e6 log-uniform; Pr 0.7-7; "
+                        "Q 0-1e-4), FP32" % len(probs),
+            "nodes": nodes, "tile": best,
+            "mlups_batched": round(mlups_batch, 1), "mlups_loop_of_launches": round(mlups_loop, 1),
+            "speedup_vs_loop": round(mlups_batch / mlups_loop, 2),
+            "run_to_residual": {"tol": 1e-7, "K": 1000, "max_steps": args.sweep_max_steps,
+                                "status_counts": counts, "seconds": round(t_run, 2),
+                                "mlups": round(lups / t_run / 1e6, 1),
+                                "steps_min": int(min(steps)), "steps_max": int(max(steps)),
+                                "steps_median": float(np.median(steps))}}
+
+
+def net_flops_per_sample(H, W, cin=8, cout=3, widths=(32, 64, 128, 256)):
+    """Multiply-add flops of one forward pass of the warm-start network (3x3 convolutions)."""
+    w1, w2, w3, w4 = widths
+    layers = [(1, cin, w1), (1, w1, w1), (2, w1, w2), (2, w2, w2), (4, w2, w3), (4, w3, w3),
+              (8, w3, w4), (8, w4, w4), (4, w4 + w3, w3), (4, w3, w3), (2, w3 + w2, w2),
+              (2, w2, w2), (1, w2 + w1, w1), (1, w1, w1), (1, w1, cout)]
+    return sum(2.0 * (H // r) * (W // r) * 9 * ci * co for r, ci, co in layers)
+
+
+def warmstart_experiment(args):
+    """Learned warm start at scale: steady states of the training cavities from the batched
+    solver, training of the network by the library's kernels, and steps to residual 1e-7
+    (and Nu) of held-out cavities from the cold start and from the network's prediction."""
+    import numpy as np
+    import torch
+    import paper_1801_04577_amd as clbm
+    from paper_1801_04577_amd import warmstart as ws
+    import workloads as W
+
+    grid = args.ws_grid
+    res = {"grid": grid}
+
+    def progress(tag):
+        t0 = time.perf_counter()
+
+        def cb(steps, status):
+            log("%s: %.0f s, running %d, converged %d, diverged %d, max_steps %d, max steps %d"
+                % (tag, time.perf_counter() - t0, status.count("running"), status.count("converged"),
+                   status.count("diverged"), status.count("max_steps"), max(steps)))
+        return cb
+
+    # training data
+    sides = tuple(int(v) for v in args.ws_train_sides.split(","))
+    sets = W.warmstart_problems(args.ws_train, seed=2024, sides=sides, square=False)
+    X, Y = [], []
+    t_gen = time.perf_counter()
+    lups = 0
+    for k0 in range(0, len(sets), args.ws_chunk_instances):
+        part = sets[k0:k0 + args.ws_chunk_instances]
+        probs = [p for p, _ in part]
+        cold = [{"T": (p["T0"] + W.noise_field(sd, p["nx"], p["ny"], 1e-4)).astype(np.float32)} for p, sd in part]
+        b = clbm.Batch(probs)
+        for i, f in enumerate(cold):
+            b.init(i, **f)
+        steps, status = b.run(max_steps=args.ws_max_steps, tol=1e-7, K=1000, chunk=20000,
+                              progress=progress("generate %d-%d" % (k0, k0 + len(part))))
+        lups += sum(st * p["nx"] * p["ny"] for st, p in zip(steps, probs))
+        ok = [i for i, s in enumerate(status) if s == "converged"]
+        Y.append(ws.targets(b, probs, ok, grid, grid))
+        X.append(ws.inputs([probs[i] for i in ok], grid, grid))
+        del b
+    X = torch.cat(X)
+    Y = torch.cat(Y)
+    t_gen = time.perf_counter() - t_gen
+    res["train_states"] = int(X.shape[0])
+    res["train_requested"] = len(sets)
+    res["generate_seconds"] = round(t_gen, 1)
+    res["generate_mlups"] = round(lups / t_gen / 1e6, 1)
+    log("warmstart: %d steady states in %.0f s" % (X.shape[0], t_gen))
+
+    # training
+    net = clbm.Net(args.ws_batch, grid, grid, ws.CIN, ws.COUT, ws.WIDTHS)
+    net.set_params(torch.from_numpy(ws.init_params(seed=0)))
+    torch.cuda.synchronize()
+    t_tr = time.perf_counter()
+    losses = ws.train(net, X, Y, steps=args.ws_train_steps, lr=2e-3, lr_final=1e-4, seed=1, log_every=200)
+    torch.cuda.synchronize()
+    t_tr = time.perf_counter() - t_tr
+    fl = 3.0 * net_flops_per_sample(grid, grid) * args.ws_batch * args.ws_train_steps
+    res["train_steps"] = args.ws_train_steps
+    res["train_batch"] = args.ws_batch
+    res["train_seconds"] = round(t_tr, 1)
+    res["train_tflops"] = round(fl / t_tr / 1e12, 2)
+    res["loss_first"] = float(np.mean(losses[:50]))
+    res["loss_last"] = float(np.mean(losses[-50:]))
+    if args.ws_save:
+        np.save(args.ws_save, net.params().cpu().numpy())
+
+    # evaluation on held-out cavities
+    tsets = W.warmstart_problems(args.ws_eval, seed=7, sides=(args.ws_eval_side,), square=True)
+    tprobs = [p for p, _ in tsets]
+    cold = [{"T": (p["T0"] + W.noise_field(sd, p["nx"], p["ny"], 1e-4)).astype(np.float32)} for p, sd in tsets]
+    out = {}
+    for key, inits in (("cold", cold), ("warm", None)):
+        if inits is None:
+            inits = ws.warm_inits(ws.predict(net, ws.inputs(tprobs, grid, grid)), tprobs)
+        b = clbm.Batch(tprobs)
+        for i, f in enumerate(inits):
+            b.init(i, **f)
+        t0 = time.perf_counter()
+        steps, status = b.run(max_steps=args.ws_max_steps_eval, tol=1e-7, K=1000, chunk=20000,
+                              progress=progress("evaluate %s" % key))
+        dt = time.perf_counter() - t0
+        nu = ws.nusselt_numbers(b, tprobs)
+        out[key] = {"steps": steps, "status": status, "nu": nu, "seconds": round(dt, 1)}
+        del b
+    both = [i for i in range(len(tprobs))
+            if out["cold"]["status"][i] == "converged" and out["warm"]["status"][i] == "converged"]
+    sc = np.array([out["cold"]["steps"][i] for i in both], dtype=float)
+    sw = np.array([out["warm"]["steps"][i] for i in both], dtype=float)
+    nc = np.array([out["cold"]["nu"][i] for i in both])
+    nw = np.array([out["warm"]["nu"][i] for i in both])
+    dnu = np.abs(nw - nc) / np.abs(nc)
+    res["eval"] = {
+        "cavities": len(tprobs), "side": args.ws_eval_side, "both_converged": len(both),
+        "cold_steps_total": int(sc.sum()), "warm_steps_total": int(sw.sum()),
+        "steps_ratio_warm_over_cold": round(float(sw.sum() / sc.sum()), 4) if len(both) else None,
+        "median_ratio": round(float(np.median(sw / sc)), 4) if len(both) else None,
+        "nu_rel_diff_max": float(dnu.max()) if len(both) else None,
+        "nu_rel_diff_mean": float(dnu.mean()) if len(both) else None,
+        "nu_within_1e-3": int((dnu < 1e-3).sum()),
+        "cold_seconds": out["cold"]["seconds"], "warm_seconds": out["warm"]["seconds"],
+        "per_instance": [{"Ra": p["meta"]["Ra"], "Pr": p["meta"]["Pr"], "Qstar": p["meta"]["Qstar"],
+                          "cold_steps": out["cold"]["steps"][i], "warm_steps": out["warm"]["steps"][i],
+                          "cold_status": out["cold"]["status"][i], "warm_status": out["warm"]["status"][i],
+                          "cold_nu": out["cold"]["nu"][i], "warm_nu": out["warm"]["nu"][i]}
+                         for i, p in enumerate(tprobs)],
+    }
+    return res
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-profiles":
         # --summarize-profiles TRACE_DB FETCH_DB WRITE_DB PRECISION N "cmd1" "cmd2" "cmd3"
@@ -220,6 +414,24 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="", help="block_x,block_y,rows,remap")
     ap.add_argument("--kernel-launches", type=int, default=200)
+    ap.add_argument("--batched", action="store_true", help="run the batched-sweep benchmark only")
+    ap.add_argument("--sweep-count", type=int, default=256)
+    ap.add_argument("--sweep-steps", type=int, default=200)
+    ap.add_argument("--sweep-max-steps", type=int, default=200000)
+    ap.add_argument("--write-cache", default="", help="path of the autotuner cache (JSON lines)")
+    ap.add_argument("--warmstart", action="store_true", help="run the learned warm-start experiment only")
+    ap.add_argument("--ws-train", type=int, default=2000)
+    ap.add_argument("--ws-train-sides", default="64,96,128")
+    ap.add_argument("--ws-chunk-instances", type=int, default=1024)
+    ap.add_argument("--ws-max-steps", type=int, default=400000)
+    ap.add_argument("--ws-max-steps-eval", type=int, default=3000000)
+    ap.add_argument("--ws-grid", type=int, default=128)
+    ap.add_argument("--ws-batch", type=int, default=32)
+    ap.add_argument("--ws-train-steps", type=int, default=3000)
+    ap.add_argument("--ws-eval", type=int, default=64)
+    ap.add_argument("--ws-eval-side", type=int, default=512)
+    ap.add_argument("--ws-save", default="")
+    ap.add_argument("--ws-out", default="")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -234,6 +446,17 @@ def main():
 
     clbm.ensure_built()
     torch.cuda.set_device(0)
+    if args.batched:
+        print(json.dumps({"metric": METRIC, "batched": batched_sweep(args)}), flush=True)
+        return
+    if args.warmstart:
+        r = warmstart_experiment(args)
+        if args.ws_out:
+            with open(args.ws_out, "w") as fh:
+                json.dump(r, fh, indent=1)
+        print(json.dumps({"metric": METRIC, "warmstart": {k: v for k, v in r.items() if k != "eval"},
+                          "eval": {k: v for k, v in r["eval"].items() if k != "per_instance"}}), flush=True)
+        return
     prob = W.cavity(args.n, Ra=1e6, Pr=0.71, Q=5e-6)
     prec = clbm.CLBM_FP16_SHIFTED if args.precision == "fp16s" else clbm.CLBM_FP32
     s = clbm.Solver(prob, prec)

@@ -172,8 +172,8 @@ clbm_status clbm_get_launch(const clbm_handle* h, clbm_launch* launch);
  * graphs of that many steps (the default is 0). */
 clbm_status clbm_set_graph(clbm_handle* h, int steps_per_graph);
 
-/* Plain device-to-device copy of `bytes` bytes (16-byte vector loads and stores,
- * grid-stride; both pointers 16-byte aligned, bytes a multiple of 16) on the given
+/* Plain device-to-device copy of `bytes` bytes (one 16-byte load and store per thread;
+ * both pointers 16-byte aligned, bytes a multiple of 16) on the given
  * stream. It is the bandwidth reference of the benchmark (a kernel whose HBM traffic
  * is known exactly) and calibrates hardware traffic counters against the step kernel.
  * Not part of the method. Asynchronous. */
@@ -211,13 +211,19 @@ clbm_status clbm_batch_init(clbm_batch* b, int i, const float* d_rho, const floa
                             const float* d_uy, const float* d_T);
 /* Advances every active instance by nsteps (asynchronous). */
 clbm_status clbm_batch_step(clbm_batch* b, int nsteps);
-/* Runs until every instance has converged (max(res_u, res_T) < tol, residuals over
- * windows of K steps), diverged (non-finite value or |u| > 0.5) or reached max_steps.
- * Convergence checks and retirement of instances run on the device inside a replayed
- * HIP graph of K steps. Synchronises. steps_out[i] is the step at which instance i
- * stopped, status_out[i] its CLBM_INST_* code; both host arrays of length n. */
-clbm_status clbm_batch_run(clbm_batch* b, long max_steps, double tol, int K, long* steps_out,
-                           int* status_out);
+/* Marks every instance running with zero steps, restores the full tile list and takes
+ * the residual snapshot of the current state (asynchronous). */
+clbm_status clbm_batch_reset(clbm_batch* b);
+/* Advances the running instances until each has converged (max(res_u, res_T) < tol, the
+ * residuals of windows of K steps), diverged (non-finite value or |u| > 0.5) or taken
+ * max_steps steps since clbm_batch_reset, or until this call has advanced budget_steps
+ * steps (budget_steps <= 0: no budget); a later call resumes. Convergence checks,
+ * retirement and compaction of the tile list run on the device inside a replayed HIP
+ * graph of K steps. Synchronises. steps_out[i] is the number of steps instance i has
+ * taken (for a retired instance, the step it stopped at), status_out[i] its CLBM_INST_*
+ * code; host arrays of length n. */
+clbm_status clbm_batch_run(clbm_batch* b, long max_steps, double tol, int K, long budget_steps,
+                           long* steps_out, int* status_out);
 clbm_status clbm_batch_macros(clbm_batch* b, int i, float* d_rho, float* d_ux, float* d_uy,
                               float* d_T);
 /* Diagnostics of instance i at its current state (mass, wall gradients and temperatures,

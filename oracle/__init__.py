@@ -33,6 +33,7 @@ class _Params(ctypes.Structure):
         ("lambda_0", ctypes.c_double), ("lambda_2", ctypes.c_double),
         ("g_beta", ctypes.c_double), ("T0", ctypes.c_double),
         ("Fx", ctypes.c_double), ("Fy", ctypes.c_double), ("Q", ctypes.c_double),
+        ("viscous_heating", ctypes.c_int),
         ("kind", ctypes.c_int * 4), ("u_wall", ctypes.c_double * 4),
         ("b1", ctypes.c_double * 4), ("b2", ctypes.c_double * 4), ("b3", ctypes.c_double * 4),
     ]
@@ -112,6 +113,7 @@ def make_params(prob):
     p.Fx = float(prob.get("Fx", 0.0))
     p.Fy = float(prob.get("Fy", 0.0))
     p.Q = float(prob.get("Q", 0.0))
+    p.viscous_heating = int(bool(prob.get("viscous_heating", False)))
     for s, side in enumerate(prob["sides"]):
         p.kind[s] = _KIND[side["kind"]]
         p.u_wall[s] = float(side.get("u_wall", 0.0))

@@ -282,13 +282,45 @@ static int make_ctx(const oracle_params* p, collide_ctx* c)
     return ORACLE_OK;
 }
 
+/* Viscous dissipation of Sec. 3.2 (Q = nu (du/dy)^2 in a channel), in general
+ * nu [(d_x u_y + d_y u_x)^2 + (d_x u_x - d_y u_y)^2] for divergence-free flow. The
+ * strain rates come from the pre-collision central moments: to first order in the
+ * Chapman-Enskog expansion k11 = -(rho c_s^2/s_nu)(d_x u_y + d_y u_x) and
+ * k20 - k02 = -(2 rho c_s^2/s_nu)(d_x u_x - d_y u_y). */
+static double dissipation(const oracle_params* p, const collide_ctx* c, const double* cen, double rho)
+{
+    double shear = -c->s_nu * cen[5] / (CS2 * rho);
+    double normal = -c->s_nu * (cen[3] - cen[4]) / (2.0 * CS2 * rho);
+    return p->nu * (shear * shear + normal * normal);
+}
+
+/* Heat source at a node: the uniform Q plus, with viscous heating, the dissipation
+ * evaluated from the pre-collision populations f (velocity from Eq. 12 with F = F_v). */
+static double local_source(const oracle_params* p, const collide_ctx* c, const double* f)
+{
+    if (!p->viscous_heating) return p->Q;
+    double rho = 0.0, jx = 0.0, jy = 0.0;
+    for (int i = 0; i < Q9; ++i) {
+        rho += f[i];
+        jx += f[i] * EX[i];
+        jy += f[i] * EY[i];
+    }
+    double ux = (jx + 0.5 * p->Fx) / rho, uy = (jy + 0.5 * p->Fy) / rho;
+    double N[Q9 * Q9], raw[Q9], cen[Q9];
+    oracle_matrix_N(ux, uy, N);
+    matvec(Q9, c->M, f, raw);
+    matvec(Q9, N, raw, cen);
+    return p->Q + dissipation(p, c, cen, rho);
+}
+
 static void collide_node(const oracle_params* p, const collide_ctx* c, const double* f,
                          const double* g, double* fp, double* gp, double* macro)
 {
     /* Eq. (25): temperature with the source correction. */
+    const double Qn = local_source(p, c, f);
     double T = 0.0;
     for (int i = 0; i < Q5; ++i) T += g[i];
-    T += 0.5 * p->Q;
+    T += 0.5 * Qn;
     /* Eq. (2): Boussinesq force, gravity along -y so -g beta (T-T0) points along +y. */
     double Fx = p->Fx;
     double Fy = p->Fy + p->g_beta * (T - p->T0);
@@ -331,7 +363,7 @@ static void collide_node(const oracle_params* p, const collide_ctx* c, const dou
     matvec(Q5, c->MT, g, rt);
     matvec(Q5, NT, rt, ct);
     double kteq[Q5] = {T, 0, 0, T * CT2, T * CT2};
-    double R[Q5] = {p->Q, 0, 0, p->Q * CT2, p->Q * CT2};
+    double R[Q5] = {Qn, 0, 0, Qn * CT2, Qn * CT2};
     double pt[Q5];
     for (int r = 0; r < Q5; ++r) {
         double s = 0.0;
@@ -398,6 +430,9 @@ int oracle_create(const oracle_params* p, oracle_sim** out)
         if (p->kind[s] == ORACLE_WALL && p->b1[s] == 0.0 && p->b2[s] == 0.0)
             return ORACLE_ERR_INVALID_ARG;
     }
+    /* The dissipation source is computed from the velocity field, which must not depend on
+     * the temperature it produces (no buoyancy). */
+    if (p->viscous_heating && p->g_beta != 0.0) return ORACLE_ERR_INVALID_ARG;
     oracle_sim* s = (oracle_sim*)calloc(1, sizeof *s);
     if (!s) return ORACLE_ERR_NOMEM;
     s->p = *p;
@@ -568,7 +603,7 @@ int oracle_macros(const oracle_sim* s, double* rho, double* ux, double* uy, doub
         const double* g = s->g + k * Q5;
         double t = 0.0;
         for (int i = 0; i < Q5; ++i) t += g[i];
-        t += 0.5 * p->Q;                                   /* Eq. (25) */
+        t += 0.5 * local_source(p, &s->c, f);              /* Eq. (25) */
         double Fx = p->Fx, Fy = p->Fy + p->g_beta * (t - p->T0); /* Eq. (2) */
         double r = 0.0, jx = 0.0, jy = 0.0;
         for (int i = 0; i < Q9; ++i) {

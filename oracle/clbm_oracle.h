@@ -48,6 +48,7 @@ typedef struct {
     double T0;        /* Boussinesq reference temperature (Eq. 2) */
     double Fx, Fy;    /* external body force F_v (Eq. 2) */
     double Q;         /* uniform heat source (Eq. 24) */
+    int viscous_heating; /* add the viscous dissipation nu * Phi to Q (Sec. 3.2); needs g_beta = 0 */
     int kind[4];      /* ORACLE_PERIODIC or ORACLE_WALL per side */
     double u_wall[4]; /* tangential speed of a moving wall (x- and x+: along y; y-, y+: along x) */
     double b1[4], b2[4], b3[4]; /* thermal wall data: b1 dT/dn + b2 T = b3, n outward */

@@ -133,7 +133,8 @@ def _declare(L):
         "clbm_batch_destroy": (None, [_VP]),
         "clbm_batch_init": (st, [_VP, ctypes.c_int, _FP, _FP, _FP, _FP]),
         "clbm_batch_step": (st, [_VP, ctypes.c_int]),
-        "clbm_batch_run": (st, [_VP, ctypes.c_long, ctypes.c_double, ctypes.c_int,
+        "clbm_batch_reset": (st, [_VP]),
+        "clbm_batch_run": (st, [_VP, ctypes.c_long, ctypes.c_double, ctypes.c_int, ctypes.c_long,
                                 ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_int)]),
         "clbm_batch_macros": (st, [_VP, ctypes.c_int, _FP, _FP, _FP, _FP]),
         "clbm_batch_residual": (st, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
@@ -405,13 +406,21 @@ class Batch:
     def step(self, n=1):
         _check(lib().clbm_batch_step(self._h, int(n)), "clbm_batch_step")
 
-    def run(self, max_steps, tol, K=1000):
-        """Returns (steps, status) per instance; status names from INST_STATUS."""
+    def run(self, max_steps, tol, K=1000, chunk=0, progress=None):
+        """Resets and runs every instance to tol (see clbm_batch_run). With chunk > 0 the
+        run proceeds in calls of at most chunk steps and progress(steps, status) is called
+        after each. Returns (steps, status) per instance; status names from INST_STATUS."""
+        _check(lib().clbm_batch_reset(self._h), "clbm_batch_reset")
         steps = (ctypes.c_long * self.n)()
         status = (ctypes.c_int * self.n)()
-        _check(lib().clbm_batch_run(self._h, int(max_steps), float(tol), int(K), steps, status),
-               "clbm_batch_run")
-        return list(steps), [INST_STATUS[s] for s in status]
+        while True:
+            _check(lib().clbm_batch_run(self._h, int(max_steps), float(tol), int(K), int(chunk), steps,
+                                        status), "clbm_batch_run")
+            names = [INST_STATUS[s] for s in status]
+            if progress is not None:
+                progress(list(steps), names)
+            if chunk <= 0 or "running" not in names:
+                return list(steps), names
 
     def macros(self, i):
         import torch

@@ -572,24 +572,29 @@ clbm_status clbm_batch_step(clbm_batch* b, int nsteps)
     return launch_batch_steps(b, nsteps);
 }
 
-clbm_status clbm_batch_run(clbm_batch* b, long max_steps, double tol, int K, long* steps_out,
-                           int* status_out)
+clbm_status clbm_batch_reset(clbm_batch* b)
 {
-    if (!b || K < 2 || (K % 2) != 0 || max_steps < 0 || !(tol >= 0.0)) return CLBM_ERR_INVALID_ARG;
-    // all instances running from the current state; snapshot for the first window
+    if (!b) return CLBM_ERR_INVALID_ARG;
     const int m = std::max(b->n, b->total_tiles);
     hipLaunchKernelGGL(k_batch_reset, dim3((m + 255) / 256), dim3(256), 0, b->stream, b->d_status,
                        b->d_steps, b->d_res, b->n, b->d_full, b->total_tiles, b->d_active, b->d_count);
     CLBM_HIP(hipGetLastError());
-    clbm_status st = launch_diag(b, 0);
-    if (st != CLBM_OK) return st;
+    return launch_diag(b, 0);  // snapshot for the first residual window
+}
+
+clbm_status clbm_batch_run(clbm_batch* b, long max_steps, double tol, int K, long budget_steps,
+                           long* steps_out, int* status_out)
+{
+    if (!b || K < 2 || (K % 2) != 0 || max_steps < 0 || !(tol >= 0.0)) return CLBM_ERR_INVALID_ARG;
     if (!b->gexec || b->graph_K != K || b->graph_tol != tol || b->graph_max != max_steps) {
-        st = build_run_graph(b, K, tol, max_steps);
+        clbm_status st = build_run_graph(b, K, tol, max_steps);
         if (st != CLBM_OK) return st;
     }
+    int count = 0;
+    CLBM_HIP(hipMemcpyAsync(&count, b->d_count, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    CLBM_HIP(hipStreamSynchronize(b->stream));
     long done = 0;
-    int count = b->total_tiles;
-    while (count > 0 && done < max_steps + K) {
+    while (count > 0 && done < max_steps + K && (budget_steps <= 0 || done < budget_steps)) {
         CLBM_HIP(hipGraphLaunch(b->gexec, b->stream));
         b->step += K;
         done += K;

@@ -63,30 +63,32 @@ __device__ __forceinline__ unsigned mix32(unsigned h)
     return h;
 }
 
-// binary16 neighbour of h (value hf) on the side of r, and the dithered choice for a
-// value hf + r given a uniform variate u in [0, 1).
-__device__ __forceinline__ __half half_dither(__half h, float hf, float r, float u)
-{
-    const unsigned short fb = __half_as_ushort(h);
-    const bool up = r > 0.f;
-    const unsigned short gb = (unsigned short)((fb & 0x7fffu) == 0u
-        ? (up ? 0x0001u : 0x8001u)
-        : ((((fb >> 15) == 0u) == up) ? fb + 1u : fb - 1u));
-    const __half g = __ushort_as_half(gb);
-    const float gap = __half2float(g) - hf;
-    return fabsf(u * gap) < fabsf(r) ? g : h;
-}
-
 // Flow populations are computed in FP32: stored as is in FP32, and with the dithered
 // rounding (hash of the FP32 bits) in binary16, whose rounding error dominates.
 template <typename S> __device__ __forceinline__ void st(S* p, float v);
 template <> __device__ __forceinline__ void st<float>(float* p, float v) { __builtin_nontemporal_store(v, p); }
 template <> __device__ __forceinline__ void st<__half>(__half* p, float v)
 {
-    const __half h = __float2half_rn(v);
-    const float hf = __half2float(h);
-    const unsigned hb = mix32(__float_as_uint(v));
-    *p = half_dither(h, hf, v - hf, (float)(hb >> 8) * (1.0f / 16777216.0f));
+    // Stochastic rounding in the integer domain: binary16 keeps 10 of the 23 fraction bits
+    // of a value with exponent >= -14 and fewer below (its grid spacing is 2^-24 there), so
+    // a hashed offset of as many bits as are dropped is added to the magnitude and those
+    // bits are cleared; the conversion of the result is exact, and the magnitude rounds up
+    // with probability equal to the dropped fraction. Below 2^-24 the two candidates are
+    // 0 and 2^-24.
+    const unsigned u = __float_as_uint(v);
+    const int e = (int)((u >> 23) & 0xffu) - 127;
+    const unsigned h = mix32(u);
+    float w;
+    if (e >= -24) {
+        const int drop = 13 + (e < -14 ? -14 - e : 0);
+        const unsigned mask = (1u << drop) - 1u;
+        w = __uint_as_float((u + (h & mask)) & ~mask);
+    } else {
+        const float a = fabsf(v) * 16777216.f;
+        const float r = (float)(h >> 8) * (1.f / 16777216.f);
+        w = copysignf(r < a ? 5.9604644775390625e-8f : 0.f, v);
+    }
+    *p = __float2half_rn(w);
 }
 
 // Storage of the temperature populations: evaluated in FP64 registers for FP32 storage

@@ -128,13 +128,13 @@ LatticeConst make_const(const clbm_params* p, const Rates& r)
 // Kernels besides the step
 // ---------------------------------------------------------------------------
 
-// Streaming copy used as the bandwidth reference (see clbm_stream_copy).
+// Streaming copy used as the bandwidth reference (see clbm_stream_copy): one 16-byte
+// element per thread.
 __global__ void __launch_bounds__(256) k_stream_copy(float4* __restrict__ dst,
                                                      const float4* __restrict__ src, size_t n)
 {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
-        dst[k] = src[k];
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = src[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -517,7 +517,8 @@ clbm_status clbm_stream_copy(void* d_dst, const void* d_src, size_t bytes, void*
         return CLBM_ERR_INVALID_ARG;
     const size_t n = bytes / 16;
     if (n == 0) return CLBM_OK;
-    const int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
+    if ((n + 255) / 256 > 0x7fffffffu) return CLBM_ERR_UNSUPPORTED;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, (hipStream_t)hip_stream,
                        (float4*)d_dst, (const float4*)d_src, n);
     CLBM_HIP(hipGetLastError());

@@ -130,20 +130,26 @@ def nusselt_numbers(batch, probs):
     return out
 
 
-def compare(net, probs, cold, grid, max_steps, tol, K):
+def compare(net, probs, cold, grid, max_steps, tol, K, refine_tol=None):
     """Cold start (initial fields `cold`, one dict per problem) and network warm start of
     the same problems to the same residual: per-instance steps, status and Nusselt
-    numbers of both."""
+    numbers of both. With refine_tol both runs are then continued to that residual and
+    their Nusselt numbers reported again (they must reach the same steady state)."""
     t0 = time.perf_counter()
     bc, steps_c, st_c = solve(probs, cold, max_steps, tol, K)
     nu_c = nusselt_numbers(bc, probs)
-    del bc
     t1 = time.perf_counter()
     X = inputs(probs, grid, grid)
     pred = predict(net, X)
     bw, steps_w, st_w = solve(probs, warm_inits(pred, probs), max_steps, tol, K)
     nu_w = nusselt_numbers(bw, probs)
     t2 = time.perf_counter()
-    return {"cold_steps": steps_c, "cold_status": st_c, "cold_nu": nu_c,
-            "warm_steps": steps_w, "warm_status": st_w, "warm_nu": nu_w,
-            "cold_seconds": t1 - t0, "warm_seconds": t2 - t1}
+    out = {"cold_steps": steps_c, "cold_status": st_c, "cold_nu": nu_c,
+           "warm_steps": steps_w, "warm_status": st_w, "warm_nu": nu_w,
+           "cold_seconds": t1 - t0, "warm_seconds": t2 - t1}
+    if refine_tol is not None:
+        for key, b in (("cold", bc), ("warm", bw)):
+            steps, status = b.run(max_steps=max_steps, tol=refine_tol, K=K)
+            out[key + "_refined_nu"] = nusselt_numbers(b, probs)
+            out[key + "_refined_status"] = status
+    return out
