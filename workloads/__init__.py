@@ -4,7 +4,8 @@ This module holds problem descriptions and seeded random inputs only: no
 lattice Boltzmann arithmetic. Both the FP64 oracle and the GPU library take
 the same plain-dict problem and the same host arrays from here.
 
-Problem dict keys: ``nx, ny, nu, alpha, g_beta, T0, Fx, Fy, Q`` and ``sides``
+Problem dict keys: ``nx, ny, nu, alpha, g_beta, T0, Fx, Fy, Q``, ``viscous_heating``
+(add the local viscous dissipation to Q, Sec. 3.2) and ``sides``
 (four dicts, order x-, x+, y-, y+: ``kind`` "periodic"/"wall", ``u_wall``,
 Robin data ``b1, b2, b3`` of ``b1 dT/dn + b2 T = b3`` with n the outward
 normal). Optional rate overrides ``s_b, s_4, s_3, lambda_0, lambda_2``.
@@ -36,10 +37,12 @@ def robin(b1, b2, b3, u_wall=0.0):
             "u_wall": float(u_wall)}
 
 
-def problem(nx, ny, nu, alpha, sides, g_beta=0.0, T0=0.0, Fx=0.0, Fy=0.0, Q=0.0, **rates):
+def problem(nx, ny, nu, alpha, sides, g_beta=0.0, T0=0.0, Fx=0.0, Fy=0.0, Q=0.0,
+            viscous_heating=False, **rates):
     p = {"nx": int(nx), "ny": int(ny), "nu": float(nu), "alpha": float(alpha),
          "g_beta": float(g_beta), "T0": float(T0), "Fx": float(Fx), "Fy": float(Fy),
-         "Q": float(Q), "sides": [dict(s) for s in sides]}
+         "Q": float(Q), "viscous_heating": bool(viscous_heating),
+         "sides": [dict(s) for s in sides]}
     for k, v in rates.items():
         assert k in ("s_b", "s_4", "s_3", "lambda_0", "lambda_2"), k
         p[k] = v
@@ -111,6 +114,30 @@ def cavity_initial_T(prob, seed=12345, amplitude=1e-4):
 def couette(nx=4, ny=16, nu=0.1, alpha=0.1, U=0.01, Tc=0.0, Th=1.0, Q=0.0):
     """Bottom wall at rest (Tc), top wall moving with U along x (Th); periodic in x."""
     return problem(nx, ny, nu, alpha, [PERIODIC, PERIODIC, dirichlet(Tc), dirichlet(Th, U)], Q=Q)
+
+
+def viscous_channel(ny, nx=4, nu=0.1, alpha=0.1, umax=0.01, Tw=0.0, transpose=False):
+    """Body-force Poiseuille flow with viscous heating (Sec. 3.2): walls at Tw, no
+    buoyancy, half-width h = ny/2, force chosen so that the centre speed is umax.
+    transpose=True turns the channel by 90 degrees (flow along y, walls at x = 0, nx)."""
+    h = ny / 2.0
+    F = 2.0 * nu * umax / (h * h)
+    walls = [dirichlet(Tw), dirichlet(Tw)]
+    if transpose:
+        p = problem(ny, nx, nu, alpha, walls + [PERIODIC, PERIODIC], Fy=F)
+    else:
+        p = problem(nx, ny, nu, alpha, [PERIODIC, PERIODIC] + walls, Fx=F)
+    p["viscous_heating"] = True
+    return p
+
+
+def viscous_channel_exact(ny, nu=0.1, alpha=0.1, umax=0.01, Tw=0.0):
+    """Steady temperature of the viscous-heating channel at the node centres
+    (Sec. 3.2): Tw + (h^2 F/2)^2 (1 - (y/h)^4)/(3 nu alpha), y from the centre line."""
+    h = ny / 2.0
+    F = 2.0 * nu * umax / (h * h)
+    y = np.arange(ny) + 0.5 - h
+    return Tw + (h * h * F / 2.0) ** 2 * (1.0 - (y / h) ** 4) / (3.0 * nu * alpha)
 
 
 # Sizes of the workloads named in the benchmark and the tests.
