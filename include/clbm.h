@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define CLBM_ABI_VERSION 1
+#define CLBM_ABI_VERSION 2
 
 typedef enum {
     CLBM_OK = 0,
@@ -87,6 +87,11 @@ typedef struct {
     double T0;          /* Boussinesq reference temperature; also the storage shift of g */
     double Fx, Fy;      /* external body force F_v (Eq. 2) */
     double Q;           /* uniform heat source (Eq. 24) */
+    int viscous_heating; /* 0 or 1: add the local viscous dissipation
+                            nu [(d_x u_y + d_y u_x)^2 + (d_x u_x - d_y u_y)^2] to Q (Sec. 3.2),
+                            evaluated from the non-equilibrium central moments k11 and
+                            k20 - k02. Requires g_beta = 0 and |1 - s_nu| >= 1e-3
+                            (nu not within about 3.3e-4 of 1/6), else CLBM_ERR_INVALID_ARG. */
     clbm_side side[4];  /* CLBM_SIDE_XM, _XP, _YM, _YP */
 } clbm_params;
 

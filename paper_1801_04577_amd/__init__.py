@@ -43,6 +43,7 @@ class clbm_params(ctypes.Structure):
         ("lambda_0", ctypes.c_double), ("lambda_2", ctypes.c_double),
         ("g_beta", ctypes.c_double), ("T0", ctypes.c_double),
         ("Fx", ctypes.c_double), ("Fy", ctypes.c_double), ("Q", ctypes.c_double),
+        ("viscous_heating", ctypes.c_int),
         ("side", clbm_side * 4),
     ]
 
@@ -197,6 +198,7 @@ def make_params(prob, precision=CLBM_FP32):
         setattr(p, k, _nan_if_none(prob.get(k)))
     for k in ("g_beta", "T0", "Fx", "Fy", "Q"):
         setattr(p, k, float(prob.get(k, 0.0)))
+    p.viscous_heating = int(bool(prob.get("viscous_heating", False)))
     for s, side in enumerate(prob["sides"]):
         p.side[s].kind = _KIND[side["kind"]]
         p.side[s].u_wall = float(side.get("u_wall", 0.0))

@@ -24,11 +24,12 @@ __global__ void __launch_bounds__(256) k_init(S* __restrict__ dst, const Lattice
     const float vy = uy ? uy[k] : 0.f;
     const float th = T ? T[k] - c.T0 : 0.f;
     float a[9], b[5];
-    typename Wide<S>::type tb[5];
+    typename Wide<S>::type fa[9], tb[5];
     equilibrium(drho, vx, vy, th, c.T0, a, b);
     NodeMacro m;
-    collide(c, a, b, tb, m);
-    store_node(dst, c, (unsigned)y * c.pitch + x, a, tb);
+    if (c.viscous) collide<typename Wide<S>::type, true>(c, a, b, fa, tb, m);
+    else collide(c, a, b, fa, tb, m);
+    store_node(dst, c, (unsigned)y * c.pitch + x, fa, tb);
 }
 
 template <typename S>
@@ -41,7 +42,7 @@ __global__ void __launch_bounds__(256) k_macros(const S* __restrict__ src, const
     if (x >= c.nx || y >= c.ny) return;
     float a[9], b[5];
     load_own(src, c, (unsigned)y * c.pitch + x, a, b);
-    const NodeMacro m = macros_from_post(c, a, b);
+    const NodeMacro m = c.viscous ? macros_from_post<true>(c, a, b) : macros_from_post(c, a, b);
     const size_t k = (size_t)y * c.nx + x;
     if (rho) rho[k] = 1.f + m.drho;
     if (ux) ux[k] = m.ux;
@@ -89,14 +90,12 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag(const S* __restrict__ src, 
     for (int k = 0; k < kDiagSums; ++k) acc[k] = 0.0;
     const size_t n = (size_t)c.nx * c.ny;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    const unsigned P = c.plane;
-    const S* gs = src + 9 * P;
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
         const int y = (int)(k / c.nx), x = (int)(k - (size_t)y * c.nx);
         const unsigned own = (unsigned)y * c.pitch + x;
         float a[9], b[5];
         load_own(src, c, own, a, b);
-        const NodeMacro m = macros_from_post(c, a, b);
+        const NodeMacro m = c.viscous ? macros_from_post<true>(c, a, b) : macros_from_post(c, a, b);
         const float T = c.T0 + m.theta;
         const bool bad = !(isfinite(m.drho) && isfinite(m.ux) && isfinite(m.uy) && isfinite(T));
         acc[0] += m.drho;
@@ -120,9 +119,7 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag(const S* __restrict__ src, 
             const int x2 = s == 0 ? x + 1 : (s == 1 ? x - 1 : x);
             const int y2 = s == 2 ? y + 1 : (s == 3 ? y - 1 : y);
             const unsigned o2 = (unsigned)y2 * c.pitch + x2;
-            float sum2 = 0.f;
-            for (int i = 0; i < 5; ++i) sum2 += ld(gs + i * P + o2);
-            const float th2 = sum2 - 0.5f * c.Q;
+            const float th2 = c.viscous ? theta_post<S, true>(src, c, o2) : theta_post<S, false>(src, c, o2);
             const float thw = c.a1[s] * m.theta + c.a2[s] * th2 + c.a3[s];
             acc[5 + s] += (8.0 * thw - 9.0 * m.theta + th2) / 3.0;
             acc[9 + s] += (double)c.T0 + thw;

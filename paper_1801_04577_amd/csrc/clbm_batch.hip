@@ -47,11 +47,16 @@ __global__ void __launch_bounds__(1024) k_batch_step(const BatchInst* __restrict
             const float* src = reinterpret_cast<const float*>(I.buf[parity]);
             float* dst = reinterpret_cast<float*>(I.buf[parity ^ 1]);
             float a[9], b[5];
-            double tb[5];
-            gather_node(src, c, x, y, a, b);
+            double fa[9], tb[5];
             NodeMacro m;
-            collide(c, a, b, tb, m);
-            store_node(dst, c, (unsigned)y * c.pitch + x, a, tb);
+            if (c.viscous) {
+                gather_node<float, true>(src, c, x, y, a, b);
+                collide<double, true>(c, a, b, fa, tb, m);
+            } else {
+                gather_node(src, c, x, y, a, b);
+                collide(c, a, b, fa, tb, m);
+            }
+            store_node(dst, c, (unsigned)y * c.pitch + x, fa, tb);
         }
     }
 }
@@ -98,7 +103,7 @@ __global__ void __launch_bounds__(1024) k_batch_diag(const BatchInst* __restrict
             float* snap = reinterpret_cast<float*>(I.snap);
             float a[9], b[5];
             load_own(src, c, (unsigned)y * c.pitch + x, a, b);
-            const NodeMacro m = macros_from_post(c, a, b);
+            const NodeMacro m = c.viscous ? macros_from_post<true>(c, a, b) : macros_from_post(c, a, b);
             const float T = c.T0 + m.theta;
             const size_t k = (size_t)y * c.nx + x, np = (size_t)c.nx * c.ny;
             const double u2 = (double)m.ux * m.ux + (double)m.uy * m.uy;

@@ -39,6 +39,9 @@ struct LatticeConst {
     float one_m_l1, one_m_l2;  // thermal 1 - lambda_1, 1 - lambda_2
     float src2;                // (1 - lambda_2/2) c_T^2 Q (source on thermal k20, k02)
     float g_beta, Fx, Fy, Q, T0;
+    int viscous;               // add the viscous dissipation to Q (Sec. 3.2)
+    float vh_pre, vh_post;     // 9 nu s_nu^2, and the same over (1 - s_nu)^2
+    float src2_q;              // (1 - lambda_2/2) c_T^2
     float uw[4];               // tangential wall speeds, side order x-, x+, y-, y+
     float a1[4], a2[4], a3[4]; // theta_w = a1 theta_1 + a2 theta_2 + a3  (Eq. 28 in theta = T - T0)
 };
@@ -91,8 +94,8 @@ template <> __device__ __forceinline__ void st<__half>(__half* p, float v)
     *p = __float2half_rn(w);
 }
 
-// Storage of the temperature populations: evaluated in FP64 registers for FP32 storage
-// and in FP32 for binary16 storage (whose rounding, 2^-11, dominates FP32's).
+// Arithmetic type of the collision for a storage type: FP64 for FP32 storage and FP32
+// for binary16 storage (whose rounding, 2^-11, dominates FP32's).
 template <typename S> struct Wide;
 template <> struct Wide<float> { typedef double type; };
 template <> struct Wide<__half> { typedef float type; };
@@ -123,10 +126,10 @@ struct NodeMacro {
 // every step, and round-to-nearest of that increment onto the storage grid would
 // otherwise bias the temperature by a fixed fraction of an ulp per step.
 template <typename R>
-__device__ __forceinline__ void collide_thermal(const LatticeConst& c, const float b[5], float uxf,
-                                                float uyf, R tb[5])
+__device__ __forceinline__ void collide_thermal(const LatticeConst& c, const float b[5], R ux,
+                                                R uy, R Q, R src2, R tb[5])
 {
-    const R ux = uxf, uy = uyf, Q = c.Q, T0 = c.T0;
+    const R T0 = c.T0;
     const R b0 = b[0], b1 = b[1], b2 = b[2], b3 = b[3], b4 = b[4];
     const R ux2 = ux * ux, uy2 = uy * uy;
     // Raw moments of b (Eq. 16); the rest weights carry [T0, 0, 0, T0 c_T^2, T0 c_T^2].
@@ -143,8 +146,8 @@ __device__ __forceinline__ void collide_thermal(const LatticeConst& c, const flo
     // lambda_2 on k20, k02 with the source (1 - lambda_2/2) c_T^2 Q.
     const R e10s = (R)c.one_m_l1 * e10;
     const R e01s = (R)c.one_m_l1 * e01;
-    const R m20s = (R)c.one_m_l2 * m20 + (R)c.src2;
-    const R m02s = (R)c.one_m_l2 * m02 + (R)c.src2;
+    const R m20s = (R)c.one_m_l2 * m20 + src2;
+    const R m02s = (R)c.one_m_l2 * m02 + src2;
     // Back to raw moments (shift by -u): k00* = T + Q/2 = T0 + Th.
     const R Th = theta + R(0.5) * Q;
     const R K00s = T0 + Th;
@@ -160,98 +163,129 @@ __device__ __forceinline__ void collide_thermal(const LatticeConst& c, const flo
     tb[4] = R(0.5) * (q02 - q01);
 }
 
-// Cascaded collision of one node. On entry a[9], b[5] hold the pre-collision
-// deviations at time t; on exit a[9] holds the post-collision flow deviations and
-// tb[5] the post-collision temperature deviations (in the wide type R, to be rounded
-// into storage by store_node). m receives rho - 1, u and T - T0 at time t.
+// Viscous dissipation nu [(d_x u_y + d_y u_x)^2 + (d_x u_x - d_y u_y)^2] (Sec. 3.2 uses
+// its channel form nu (du/dy)^2) from the non-equilibrium central second moments of the
+// flow populations. To first order in the Chapman-Enskog expansion the pre-collision
+// k11 = -(rho/(3 s_nu))(d_x u_y + d_y u_x) and k20 - k02 = -(2 rho/(3 s_nu))(d_x u_x - d_y u_y),
+// so the dissipation is coef (k11^2 + (k20 - k02)^2/4)/rho^2 with coef = 9 nu s_nu^2.
+// The post-collision moments are (1 - s_nu) times the pre-collision ones (the force term
+// has no second-order central part), hence coef/(1 - s_nu)^2 on stored data.
 template <typename R>
-__device__ __forceinline__ void collide(const LatticeConst& c, float a[9], const float b[5], R tb[5],
-                                        NodeMacro& m)
+__device__ __forceinline__ R dissipation(float coef, R c11, R c2d, R rho)
 {
+    const R h = R(0.5) * c2d;
+    return (R)coef * (c11 * c11 + h * h) / (rho * rho);
+}
+
+// Cascaded collision of one node. On entry a[9], b[5] hold the pre-collision
+// deviations at time t; on exit fa[9] and tb[5] hold the post-collision flow and
+// temperature deviations in the wide type R, to be rounded into storage by store_node.
+// m receives rho - 1, u and T - T0 at time t.
+// R is wider than the storage (FP64 for FP32 storage, FP32 for FP16 storage) so that the
+// only rounding left in a time step is the unbiased one into storage: a body force or a
+// heat source adds the same non-representable amount every step, and round-to-nearest of
+// those increments in storage-precision arithmetic would otherwise bias the velocity and
+// the temperature by a fixed fraction of an ulp per step.
+// VH: the heat source is Q plus the local viscous dissipation (needs g_beta = 0, so
+// that the force does not depend on the temperature the source produces).
+template <typename R, bool VH = false>
+__device__ __forceinline__ void collide(const LatticeConst& c, const float a_in[9], const float b[5],
+                                        R fa[9], R tb[5], NodeMacro& m)
+{
+    const R third = R(1) / R(3), ninth = R(1) / R(9);
     // Eq. (25): T = sum g + Q/2; sum g = T0 + sum b.
     const float sb = (b[0] + b[1]) + (b[2] + b[3]) + b[4];
     const float theta = sb + 0.5f * c.Q;
     // Eq. (2): gravity along -y.
-    const float Fx = c.Fx;
-    const float Fy = c.Fy + c.g_beta * theta;
+    const R Fx = c.Fx;
+    const R Fy = (R)c.Fy + (R)c.g_beta * (R)theta;
+    R a[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) a[i] = a_in[i];
 
     // Raw moments of the deviations (Eq. 6a applied to a); the rest weights carry
     // [1, 0, 0, 1/3, 1/3, 0, 0, 0, 1/9].
-    const float s13 = a[1] + a[3], d13 = a[1] - a[3];
-    const float s24 = a[2] + a[4], d24 = a[2] - a[4];
-    const float p56 = a[5] + a[6], m56 = a[5] - a[6];
-    const float p78 = a[7] + a[8], m78 = a[7] - a[8];
-    const float k22 = p56 + p78;                    // a5 + a6 + a7 + a8
-    const float d = a[0] + s13 + s24 + k22;         // rho - 1
-    const float jx = d13 + m56 - m78;               // k10
-    const float jy = d24 + p56 - p78;               // k01
-    const float k20 = s13 + k22;
-    const float k02 = s24 + k22;
-    const float k11 = m56 + m78;
-    const float k21 = p56 - p78;
-    const float k12 = m56 - m78;
+    const R s13 = a[1] + a[3], d13 = a[1] - a[3];
+    const R s24 = a[2] + a[4], d24 = a[2] - a[4];
+    const R p56 = a[5] + a[6], m56 = a[5] - a[6];
+    const R p78 = a[7] + a[8], m78 = a[7] - a[8];
+    const R k22 = p56 + p78;                    // a5 + a6 + a7 + a8
+    const R d = a[0] + s13 + s24 + k22;         // rho - 1
+    const R jx = d13 + m56 - m78;               // k10
+    const R jy = d24 + p56 - p78;               // k01
+    const R k20 = s13 + k22;
+    const R k02 = s24 + k22;
+    const R k11 = m56 + m78;
+    const R k21 = p56 - p78;
+    const R k12 = m56 - m78;
 
     // Eq. (12).
-    const float rho = 1.f + d;
-    const float inv = 1.f / rho;
-    const float ux = (jx + 0.5f * Fx) * inv;
-    const float uy = (jy + 0.5f * Fy) * inv;
-    const float ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+    const R rho = R(1) + d;
+    const R inv = R(1) / rho;
+    const R ux = (jx + R(0.5) * Fx) * inv;
+    const R uy = (jy + R(0.5) * Fy) * inv;
+    const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
 
     // Central moments (Eq. 6b), minus their equilibria (Eq. 9).
-    const float c10 = jx - ux * rho;
-    const float c01 = jy - uy * rho;
-    const float K20 = (1.f / 3.f) + k20;           // full raw k20
-    const float K02 = (1.f / 3.f) + k02;
-    const float n20 = (k20 - d * (1.f / 3.f)) - 2.f * ux * jx + ux2 * rho;
-    const float n02 = (k02 - d * (1.f / 3.f)) - 2.f * uy * jy + uy2 * rho;
-    const float c11 = k11 - uy * jx - ux * jy + uxy * rho;
-    const float c21 = k21 - 2.f * ux * k11 - uy * K20 + 2.f * uxy * jx + ux2 * jy - ux2 * uy * rho;
-    const float c12 = k12 - 2.f * uy * k11 - ux * K02 + 2.f * uxy * jy + uy2 * jx - uy2 * ux * rho;
-    const float n22 = (k22 - d * (1.f / 9.f)) - 2.f * ux * k12 - 2.f * uy * k21 + 4.f * uxy * k11
-                      + uy2 * K20 + ux2 * K02 - 2.f * ux * uy2 * jx - 2.f * ux2 * uy * jy
-                      + ux2 * uy2 * rho;
+    const R c10 = jx - ux * rho;
+    const R c01 = jy - uy * rho;
+    const R K20 = third + k20;                  // full raw k20
+    const R K02 = third + k02;
+    const R n20 = (k20 - d * third) - R(2) * ux * jx + ux2 * rho;
+    const R n02 = (k02 - d * third) - R(2) * uy * jy + uy2 * rho;
+    const R c11 = k11 - uy * jx - ux * jy + uxy * rho;
+    const R c21 = k21 - R(2) * ux * k11 - uy * K20 + R(2) * uxy * jx + ux2 * jy - ux2 * uy * rho;
+    const R c12 = k12 - R(2) * uy * k11 - ux * K02 + R(2) * uxy * jy + uy2 * jx - uy2 * ux * rho;
+    const R n22 = (k22 - d * ninth) - R(2) * ux * k12 - R(2) * uy * k21 + R(4) * uxy * k11
+                  + uy2 * K20 + ux2 * K02 - R(2) * ux * uy2 * jx - R(2) * ux2 * uy * jy
+                  + ux2 * uy2 * rho;
 
     // Eq. (7): relaxation with the force term (I - S/2) C; rows 0-2 are not relaxed.
-    const float c10s = c10 + Fx;
-    const float c01s = c01 + Fy;
-    const float n20s = c.one_m_sp * n20 - c.sm * n02;
-    const float n02s = c.one_m_sp * n02 - c.sm * n20;
-    const float c11s = c.one_m_snu * c11;
-    const float c21s = c.one_m_s3 * c21 + c.half_s3c * Fy;
-    const float c12s = c.one_m_s3 * c12 + c.half_s3c * Fx;
-    const float n22s = c.one_m_s4 * n22;
+    const R c10s = c10 + Fx;
+    const R c01s = c01 + Fy;
+    const R n20s = c.one_m_sp * n20 - c.sm * n02;
+    const R n02s = c.one_m_sp * n02 - c.sm * n20;
+    const R c11s = c.one_m_snu * c11;
+    const R c21s = c.one_m_s3 * c21 + c.half_s3c * Fy;
+    const R c12s = c.one_m_s3 * c12 + c.half_s3c * Fx;
+    const R n22s = c.one_m_s4 * n22;
 
     // Back to raw moments (shift by -u), minus the rest-weight moments.
-    const float K20s = (1.f / 3.f) + d * (1.f / 3.f) + n20s;   // full central k20*
-    const float K02s = (1.f / 3.f) + d * (1.f / 3.f) + n02s;
-    const float r10 = c10s + ux * rho;
-    const float r01 = c01s + uy * rho;
-    const float r20 = d * (1.f / 3.f) + n20s + 2.f * ux * c10s + ux2 * rho;
-    const float r02 = d * (1.f / 3.f) + n02s + 2.f * uy * c01s + uy2 * rho;
-    const float r11 = c11s + uy * c10s + ux * c01s + uxy * rho;
-    const float r21 = c21s + 2.f * ux * c11s + uy * K20s + 2.f * uxy * c10s + ux2 * c01s + ux2 * uy * rho;
-    const float r12 = c12s + 2.f * uy * c11s + ux * K02s + 2.f * uxy * c01s + uy2 * c10s + uy2 * ux * rho;
-    const float r22 = d * (1.f / 9.f) + n22s + 2.f * ux * c12s + 2.f * uy * c21s + 4.f * uxy * c11s
-                      + uy2 * K20s + ux2 * K02s + 2.f * ux * uy2 * c10s + 2.f * ux2 * uy * c01s
-                      + ux2 * uy2 * rho;
+    const R K20s = third + d * third + n20s;    // full central k20*
+    const R K02s = third + d * third + n02s;
+    const R r10 = c10s + ux * rho;
+    const R r01 = c01s + uy * rho;
+    const R r20 = d * third + n20s + R(2) * ux * c10s + ux2 * rho;
+    const R r02 = d * third + n02s + R(2) * uy * c01s + uy2 * rho;
+    const R r11 = c11s + uy * c10s + ux * c01s + uxy * rho;
+    const R r21 = c21s + R(2) * ux * c11s + uy * K20s + R(2) * uxy * c10s + ux2 * c01s + ux2 * uy * rho;
+    const R r12 = c12s + R(2) * uy * c11s + ux * K02s + R(2) * uxy * c01s + uy2 * c10s + uy2 * ux * rho;
+    const R r22 = d * ninth + n22s + R(2) * ux * c12s + R(2) * uy * c21s + R(4) * uxy * c11s
+                  + uy2 * K20s + ux2 * K02s + R(2) * ux * uy2 * c10s + R(2) * ux2 * uy * c01s
+                  + ux2 * uy2 * rho;
 
     // Inverse of Eq. (6a).
-    a[0] = d - r20 - r02 + r22;
-    a[1] = 0.5f * (r10 + r20 - r12 - r22);
-    a[3] = 0.5f * (-r10 + r20 + r12 - r22);
-    a[2] = 0.5f * (r01 + r02 - r21 - r22);
-    a[4] = 0.5f * (-r01 + r02 + r21 - r22);
-    a[5] = 0.25f * (r11 + r21 + r12 + r22);
-    a[6] = 0.25f * (-r11 + r21 - r12 + r22);
-    a[7] = 0.25f * (r11 - r21 - r12 + r22);
-    a[8] = 0.25f * (-r11 - r21 + r12 + r22);
+    fa[0] = d - r20 - r02 + r22;
+    fa[1] = R(0.5) * (r10 + r20 - r12 - r22);
+    fa[3] = R(0.5) * (-r10 + r20 + r12 - r22);
+    fa[2] = R(0.5) * (r01 + r02 - r21 - r22);
+    fa[4] = R(0.5) * (-r01 + r02 + r21 - r22);
+    fa[5] = R(0.25) * (r11 + r21 + r12 + r22);
+    fa[6] = R(0.25) * (-r11 + r21 - r12 + r22);
+    fa[7] = R(0.25) * (r11 - r21 - r12 + r22);
+    fa[8] = R(0.25) * (-r11 - r21 + r12 + r22);
 
-    collide_thermal(c, b, ux, uy, tb);
-    m.drho = d;
-    m.ux = ux;
-    m.uy = uy;
-    m.theta = theta;
+    if constexpr (VH) {
+        const R Qn = (R)c.Q + dissipation<R>(c.vh_pre, c11, n20 - n02, rho);
+        collide_thermal(c, b, ux, uy, Qn, (R)c.src2_q * Qn, tb);
+        m.theta = (float)((R)sb + R(0.5) * Qn);
+    } else {
+        collide_thermal(c, b, ux, uy, (R)c.Q, (R)c.src2, tb);
+        m.theta = theta;
+    }
+    m.drho = (float)d;
+    m.ux = (float)ux;
+    m.uy = (float)uy;
 }
 
 // Discrete equilibria of Eq. (9) and Eq. (19) at (rho, u, T) as deviations.
@@ -291,7 +325,9 @@ __device__ __forceinline__ void equilibrium(float drho, float ux, float uy, floa
 
 // Macroscopic values at time t from the stored post-collision deviations at t:
 // collision conserves rho, adds F to the momentum and Q to sum g, so
-// T = sum g* - Q/2 and u = (sum f* e - F/2)/rho.
+// T = sum g* - Q/2 and u = (sum f* e - F/2)/rho. With VH the Q of the node is
+// recovered from the post-collision central moments at that u.
+template <bool VH = false>
 __device__ __forceinline__ NodeMacro macros_from_post(const LatticeConst& c, const float a[9],
                                                       const float b[5])
 {
@@ -309,6 +345,16 @@ __device__ __forceinline__ NodeMacro macros_from_post(const LatticeConst& c, con
     m.drho = d;
     m.ux = (jx - 0.5f * Fx) * inv;
     m.uy = (jy - 0.5f * Fy) * inv;
+    if constexpr (VH) {
+        // Central k11 and k20 - k02 of the post-collision deviations (the rest weights
+        // contribute to neither).
+        const float rho = 1.f + d;
+        const float k11 = m56 + m78;
+        const float k2d = (a[1] + a[3]) - (a[2] + a[4]);
+        const float c11 = k11 - m.uy * jx - m.ux * jy + m.ux * m.uy * rho;
+        const float c2d = k2d - 2.f * m.ux * jx + 2.f * m.uy * jy + (m.ux * m.ux - m.uy * m.uy) * rho;
+        m.theta -= 0.5f * dissipation<float>(c.vh_post, c11, c2d, rho);
+    }
     return m;
 }
 

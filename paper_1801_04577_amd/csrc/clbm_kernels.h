@@ -12,9 +12,42 @@
 
 namespace clbm {
 
+// The 14 stored populations of one node.
+template <typename S>
+__device__ __forceinline__ void load_own(const S* __restrict__ src, const LatticeConst& c,
+                                         unsigned own, float a[9], float b[5])
+{
+    const unsigned P = c.plane;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) a[i] = ld(src + i * P + own);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) b[i] = ld(src + (9 + i) * P + own);
+}
+
+// T - T0 at time t of the node at element offset off, from its stored post-collision
+// populations: sum g* - Q/2, with Q the node's own source under VH.
+template <typename S, bool VH>
+__device__ __forceinline__ float theta_post(const S* __restrict__ src, const LatticeConst& c,
+                                            unsigned off)
+{
+    const unsigned P = c.plane;
+    const S* gs = src + 9 * P;
+    if constexpr (VH) {
+        float a[9], b[5];
+        load_own(src, c, off, a, b);
+        return macros_from_post<true>(c, a, b).theta;
+    } else {
+        const float s = ld(gs + off) + ld(gs + P + off) + ld(gs + 2 * P + off) + ld(gs + 3 * P + off)
+                        + ld(gs + 4 * P + off);
+        return s - 0.5f * c.Q;
+    }
+}
+
 // Gather the pre-collision deviations of node (x, y) at time t+1 from the
 // post-collision buffer at time t, with all wall substitutions applied.
-template <typename S>
+// VH: the heat source includes the viscous dissipation (wall temperatures need the
+// source of the nodes they are extrapolated from).
+template <typename S, bool VH = false>
 __device__ __forceinline__ void gather_node(const S* __restrict__ src, const LatticeConst& c, int x,
                                             int y, float a[9], float b[5])
 {
@@ -54,11 +87,7 @@ __device__ __forceinline__ void gather_node(const S* __restrict__ src, const Lat
         // Eq. (26): g_i(x_f, t+1) = -g*_opp(i)(x_f, t) + c_T^2 T_w, with T_w from Eq. (28)
         // using T at this node (T1) and one node further from the wall (T2) at time t.
         // Stored post-collision data give T = sum g* - Q/2 (the collision adds Q).
-        auto theta_at = [&](unsigned off) {
-            float s = ld(gs + off) + ld(gs + P + off) + ld(gs + 2 * P + off) + ld(gs + 3 * P + off)
-                      + ld(gs + 4 * P + off);
-            return s - 0.5f * c.Q;
-        };
+        auto theta_at = [&](unsigned off) { return theta_post<S, VH>(src, c, off); };
         const float th1 = theta_at(own);
         if (oxm) {
             const float tw = c.a1[0] * th1 + c.a2[0] * theta_at(rC + x + 1) + c.a3[0];
@@ -95,30 +124,20 @@ __device__ __forceinline__ void gather_node(const S* __restrict__ src, const Lat
     }
 }
 
-// Store the post-collision state of one node: flow deviations rounded to nearest,
-// temperature deviations (computed wider than the storage) with the unbiased rounding of
-// st_dither.
+// Store the post-collision state of one node: the deviations, computed wider than the
+// storage, with the unbiased rounding of st_dither.
 template <typename S>
 __device__ __forceinline__ void store_node(S* __restrict__ dst, const LatticeConst& c, unsigned own,
-                                           const float a[9], const typename Wide<S>::type tb[5])
+                                           const typename Wide<S>::type fa[9],
+                                           const typename Wide<S>::type tb[5])
 {
     const unsigned P = c.plane;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) st(dst + i * P + own, a[i]);
+    for (int i = 0; i < 9; ++i) st_dither(dst + i * P + own, fa[i]);
 #pragma unroll
     for (int i = 0; i < 5; ++i) st_dither(dst + (9 + i) * P + own, tb[i]);
 }
 
-template <typename S>
-__device__ __forceinline__ void load_own(const S* __restrict__ src, const LatticeConst& c,
-                                         unsigned own, float a[9], float b[5])
-{
-    const unsigned P = c.plane;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) a[i] = ld(src + i * P + own);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) b[i] = ld(src + (9 + i) * P + own);
-}
 
 // Tile -> workgroup map. With xcd_remap the grid is padded to a multiple of 8 and
 // workgroup b (dispatched to XCD b % 8) takes tile (b % 8) * (grid/8) + b/8, so
@@ -131,7 +150,7 @@ __device__ __forceinline__ int tile_of_block(int total, int remap)
     return (b & 7) * per + (b >> 3);
 }
 
-template <typename S, int ROWS>
+template <typename S, int ROWS, bool VH>
 __global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __restrict__ dst,
                                                const LatticeConst c, int tiles_x, int tiles_total,
                                                int remap)
@@ -147,11 +166,11 @@ __global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __r
         const int y = y0 + r;
         if (y < c.ny) {
             float a[9], b[5];
-            typename Wide<S>::type tb[5];
-            gather_node(src, c, x, y, a, b);
+            typename Wide<S>::type fa[9], tb[5];
+            gather_node<S, VH>(src, c, x, y, a, b);
             NodeMacro m;
-            collide(c, a, b, tb, m);
-            store_node(dst, c, (unsigned)y * c.pitch + x, a, tb);
+            collide<typename Wide<S>::type, VH>(c, a, b, fa, tb, m);
+            store_node(dst, c, (unsigned)y * c.pitch + x, fa, tb);
         }
     }
 }

@@ -73,6 +73,7 @@ clbm_status validate(const clbm_params* p, Rates* r)
     }
     if (p->side[0].kind != p->side[1].kind || p->side[2].kind != p->side[3].kind)
         return CLBM_ERR_INVALID_ARG;
+    if (p->viscous_heating != 0 && p->viscous_heating != 1) return CLBM_ERR_INVALID_ARG;
     // Eq. (27) needs a second layer of nodes next to each wall.
     if (p->side[0].kind == CLBM_WALL && p->nx < 2) return CLBM_ERR_INVALID_ARG;
     if (p->side[2].kind == CLBM_WALL && p->ny < 2) return CLBM_ERR_INVALID_ARG;
@@ -80,8 +81,14 @@ clbm_status validate(const clbm_params* p, Rates* r)
     const double elems = 14.0 * (double)p->ny * (double)row_pitch(p->nx);
     if (elems >= 4294967295.0) return CLBM_ERR_UNSUPPORTED;
     Rates tmp;
-    clbm_status st = derive_rates(p, r ? r : &tmp);
-    return st;
+    Rates* rr = r ? r : &tmp;
+    clbm_status st = derive_rates(p, rr);
+    if (st != CLBM_OK) return st;
+    // The dissipation source needs a temperature-independent flow, and its recovery
+    // from stored post-collision moments divides by 1 - s_nu.
+    if (p->viscous_heating && (p->g_beta != 0.0 || std::fabs(1.0 - rr->s_nu) < 1e-3))
+        return CLBM_ERR_INVALID_ARG;
+    return CLBM_OK;
 }
 
 LatticeConst make_const(const clbm_params* p, const Rates& r)
@@ -104,6 +111,13 @@ LatticeConst make_const(const clbm_params* p, const Rates& r)
     c.one_m_l1 = (float)(1.0 - r.l1);
     c.one_m_l2 = (float)(1.0 - r.l2);
     c.src2 = (float)((1.0 - 0.5 * r.l2) * 0.4 * p->Q);
+    c.src2_q = (float)((1.0 - 0.5 * r.l2) * 0.4);
+    c.viscous = p->viscous_heating ? 1 : 0;
+    if (c.viscous) {
+        const double coef = 9.0 * p->nu * r.s_nu * r.s_nu;
+        c.vh_pre = (float)coef;
+        c.vh_post = (float)(coef / ((1.0 - r.s_nu) * (1.0 - r.s_nu)));
+    }
     c.g_beta = (float)p->g_beta;
     c.Fx = (float)p->Fx;
     c.Fy = (float)p->Fy;
@@ -147,21 +161,27 @@ struct StepLaunch {
     int tiles_x, tiles_total, remap;
 };
 
-template <typename S>
+template <typename S, bool VH>
 static const void* step_fn(int rows)
 {
     switch (rows) {
-        case 2: return reinterpret_cast<const void*>(&k_step<S, 2>);
-        case 4: return reinterpret_cast<const void*>(&k_step<S, 4>);
-        default: return reinterpret_cast<const void*>(&k_step<S, 1>);
+        case 2: return reinterpret_cast<const void*>(&k_step<S, 2, VH>);
+        case 4: return reinterpret_cast<const void*>(&k_step<S, 4, VH>);
+        default: return reinterpret_cast<const void*>(&k_step<S, 1, VH>);
     }
+}
+
+template <typename S>
+static const void* step_fn(int rows, bool viscous)
+{
+    return viscous ? step_fn<S, true>(rows) : step_fn<S, false>(rows);
 }
 
 static StepLaunch plan_step(const LatticeConst& c, int precision, const clbm_launch& L)
 {
     StepLaunch s;
-    s.fn = precision == CLBM_FP16_SHIFTED ? step_fn<__half>(L.rows_per_thread)
-                                          : step_fn<float>(L.rows_per_thread);
+    s.fn = precision == CLBM_FP16_SHIFTED ? step_fn<__half>(L.rows_per_thread, c.viscous != 0)
+                                          : step_fn<float>(L.rows_per_thread, c.viscous != 0);
     s.block = dim3(L.block_x, L.block_y, 1);
     s.tiles_x = (c.nx + L.block_x - 1) / L.block_x;
     const int rows_per_tile = L.block_y * L.rows_per_thread;

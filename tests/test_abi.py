@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version(L):
-    assert clbm.clbm_abi_version() == 1
+    assert clbm.clbm_abi_version() == 2
 
 
 PROBLEMS = [
@@ -90,6 +90,13 @@ def test_workspace_and_validation(L):
     q.side[2].b1, q.side[2].b2 = 0.0, 0.0                 # Robin data undefined
     assert L.clbm_workspace_bytes(ctypes.byref(q), ctypes.byref(size)) == -1
     assert clbm.status_string(-3) == "workspace too small"
+    # Viscous heating (Sec. 3.2): flag 0/1 only, no buoyancy, s_nu away from 1.
+    chan = W.viscous_channel(16)
+    assert status(chan) == 0
+    assert status(chan, viscous_heating=2) == -1
+    assert status(chan, g_beta=1e-4) == -1
+    assert status(chan, nu=1.0 / 6.0) == -1
+    assert status(chan, nu=1.0 / 6.0 + 1e-3) == 0
 
 
 def test_create_rejects_small_workspace(L):

@@ -98,3 +98,28 @@ def test_cavity_256_to_residual():
     q = table1_quantities(s, d, prob)
     print("256^2 Ra 1e5: steps %d res_u %.2e res_T %.2e %s" % (s.t, d.res_u, d.res_T, q), flush=True)
     assert q["Nu"] == pytest.approx(4.5178, rel=1.5e-2)
+
+
+@pytest.mark.parametrize("alpha,best", [(0.1, 0.75), (1.0 / 3.0, 4.0 / 3.0)])
+def test_lambda2_sweep_batched(alpha, best):
+    """Fig. 2 on the GPU: the lambda_2 sweep of the Sec. 3.1 source problem as one batch
+    (one instance per lambda_2). The error is smallest at Cui's value (3/4 for
+    alpha = 1/10, 4/3 for alpha = 1/3), where the scheme is exact up to FP32 rounding."""
+    import paper_1801_04577_amd as clbm
+    grid = sorted(set(np.round(np.linspace(0.2, 1.8, 17), 12)) | {0.75, 4.0 / 3.0})
+    probs = [W.diffusion_source(alpha, W.dirichlet(0.0), W.dirichlet(1.0), lambda_2=l2) for l2 in grid]
+    b = clbm.Batch(probs)
+    for i in range(len(probs)):
+        b.init(i)
+    b.step(8000)
+    exact = W.diffusion_source_exact()
+    errs = []
+    for i in range(len(probs)):
+        T = b.macros(i)[3].cpu().numpy().astype(np.float64)[:, 0]
+        errs.append(math.sqrt(float(np.sum((T - exact) ** 2) / np.sum(exact ** 2))))
+    k = int(np.argmin(errs))
+    print("alpha %.4f: argmin lambda_2 = %.4f, E2 %.2e, next %.2e"
+          % (alpha, grid[k], errs[k], sorted(errs)[1]), flush=True)
+    assert grid[k] == pytest.approx(best, abs=1e-12)
+    assert errs[k] < 1e-6
+    assert sorted(errs)[1] > 1e-5

@@ -107,3 +107,29 @@ def test_poiseuille_turned_channel():
     scale = float(np.max(np.abs(T1)))
     assert np.max(np.abs(T1 - T2)) < 1e-9 * scale
     assert np.max(np.abs(u1 - u2)) < 1e-9 * float(np.max(np.abs(u1)))
+
+
+def couette_T_error(U, ny=16, Tc=0.0, Th=0.0, nu=0.1, alpha=0.1):
+    """Thermal Couette flow with viscous heating: the uniform shear U/H dissipates
+    nu U^2/H^2 everywhere, so the steady temperature is the conduction line plus the
+    parabola nu U^2 y (H - y)/(2 alpha H^2) (a closed form of Eq. 1c with a uniform source)."""
+    p = W.couette(nx=4, ny=ny, nu=nu, alpha=alpha, U=U, Tc=Tc, Th=Th)
+    p["viscous_heating"] = True
+    s = oracle.Sim(p, nthreads=1)
+    s.step(int(8 * ny * ny / min(nu, alpha)))
+    T = s.macros()[3][:, 0]
+    y = np.arange(ny) + 0.5
+    heat = nu * U * U / (2 * alpha * ny * ny) * y * (ny - y)
+    Ta = Tc + (Th - Tc) * y / ny + heat
+    return float(np.abs(T - Ta).max() / np.abs(heat).max())
+
+
+def test_couette_viscous_heating_closed_form():
+    e1 = couette_T_error(0.01)
+    e2_ = couette_T_error(0.02)
+    e_walls = couette_T_error(0.01, Tc=-0.001, Th=0.002)
+    print("Couette heating errors", e1, e2_, e_walls)
+    # The only departure is the O(Ma^2) compressibility error of the flow, so it is small
+    # and grows as U^2.
+    assert e1 < 2e-6 and e_walls < 2e-6
+    assert 3.5 < e2_ / e1 < 4.5

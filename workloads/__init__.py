@@ -116,6 +116,19 @@ def couette(nx=4, ny=16, nu=0.1, alpha=0.1, U=0.01, Tc=0.0, Th=1.0, Q=0.0):
     return problem(nx, ny, nu, alpha, [PERIODIC, PERIODIC, dirichlet(Tc), dirichlet(Th, U)], Q=Q)
 
 
+def diffusion_source(alpha, bottom, top, L=6, dT=1.0, **rates):
+    """Steady diffusion with a uniform heat source between two walls (Sec. 3.1): one
+    periodic column of L nodes, Q = 2 alpha dT / L^2, so that with T = 0 at the bottom
+    and T = dT at the top the steady profile is T = dT (y/L)(2 - y/L)."""
+    Q = 2.0 * alpha * dT / L ** 2
+    return problem(1, L, 0.1, alpha, [PERIODIC, PERIODIC, bottom, top], Q=Q, **rates)
+
+
+def diffusion_source_exact(L=6, T0=0.0, dT=1.0):
+    y = np.arange(L) + 0.5
+    return T0 + dT * (y / L) * (2.0 - y / L)
+
+
 def viscous_channel(ny, nx=4, nu=0.1, alpha=0.1, umax=0.01, Tw=0.0, transpose=False):
     """Body-force Poiseuille flow with viscous heating (Sec. 3.2): walls at Tw, no
     buoyancy, half-width h = ny/2, force chosen so that the centre speed is umax.
