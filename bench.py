@@ -286,27 +286,14 @@ def net_flops_per_sample(H, W, cin=8, cout=3, widths=(32, 64, 128, 256)):
     return sum(2.0 * (H // r) * (W // r) * 9 * ci * co for r, ci, co in layers)
 
 
-def warmstart_experiment(args):
-    """Learned warm start at scale: steady states of the training cavities from the batched
-    solver, training of the network by the library's kernels, and steps to residual 1e-7
-    (and Nu) of held-out cavities from the cold start and from the network's prediction."""
+def train_network(args, res, net, grid, progress):
+    """Training half of the warm-start experiment: steady states of the training cavities
+    from the batched solver (cold starts to residual 1e-7), then Adam on the network."""
     import numpy as np
     import torch
     import paper_1801_04577_amd as clbm
     from paper_1801_04577_amd import warmstart as ws
     import workloads as W
-
-    grid = args.ws_grid
-    res = {"grid": grid}
-
-    def progress(tag):
-        t0 = time.perf_counter()
-
-        def cb(steps, status):
-            log("%s: %.0f s, running %d, converged %d, diverged %d, max_steps %d, max steps %d"
-                % (tag, time.perf_counter() - t0, status.count("running"), status.count("converged"),
-                   status.count("diverged"), status.count("max_steps"), max(steps)))
-        return cb
 
     # training data
     sides = tuple(int(v) for v in args.ws_train_sides.split(","))
@@ -338,7 +325,6 @@ def warmstart_experiment(args):
     log("warmstart: %d steady states in %.0f s" % (X.shape[0], t_gen))
 
     # training
-    net = clbm.Net(args.ws_batch, grid, grid, ws.CIN, ws.COUT, ws.WIDTHS)
     net.set_params(torch.from_numpy(ws.init_params(seed=0)))
     torch.cuda.synchronize()
     t_tr = time.perf_counter()
@@ -354,6 +340,37 @@ def warmstart_experiment(args):
     res["loss_last"] = float(np.mean(losses[-50:]))
     if args.ws_save:
         np.save(args.ws_save, net.params().cpu().numpy())
+
+
+def warmstart_experiment(args):
+    """Learned warm start at scale: steady states of the training cavities from the batched
+    solver, training of the network by the library's kernels, and steps to residual 1e-7
+    (and Nu) of held-out cavities from the cold start and from the network's prediction."""
+    import numpy as np
+    import torch
+    import paper_1801_04577_amd as clbm
+    from paper_1801_04577_amd import warmstart as ws
+    import workloads as W
+
+    grid = args.ws_grid
+    res = {"grid": grid}
+
+    def progress(tag):
+        t0 = time.perf_counter()
+
+        def cb(steps, status):
+            log("%s: %.0f s, running %d, converged %d, diverged %d, max_steps %d, max steps %d"
+                % (tag, time.perf_counter() - t0, status.count("running"), status.count("converged"),
+                   status.count("diverged"), status.count("max_steps"), max(steps)))
+        return cb
+
+    net = clbm.Net(args.ws_batch, grid, grid, ws.CIN, ws.COUT, ws.WIDTHS)
+    if args.ws_load:
+        # parameters written by an earlier run of this experiment (--ws-save)
+        net.set_params(torch.from_numpy(np.load(args.ws_load, allow_pickle=False).astype(np.float32)))
+        res["params_loaded_from"] = args.ws_load
+    else:
+        train_network(args, res, net, grid, progress)
 
     # evaluation on held-out cavities
     tsets = W.warmstart_problems(args.ws_eval, seed=7, sides=(args.ws_eval_side,), square=True)
@@ -372,6 +389,15 @@ def warmstart_experiment(args):
         dt = time.perf_counter() - t0
         nu = ws.nusselt_numbers(b, tprobs)
         out[key] = {"steps": steps, "status": status, "nu": nu, "seconds": round(dt, 1)}
+        if args.ws_refine_tol > 0:
+            # continue from the state at 1e-7 to the tighter residual: both starts must
+            # reach the same steady state
+            t0 = time.perf_counter()
+            steps_r, status_r = b.run(max_steps=args.ws_max_steps_eval, tol=args.ws_refine_tol, K=1000,
+                                      chunk=20000, progress=progress("refine %s" % key))
+            out[key].update(refine_steps=steps_r, refine_status=status_r,
+                            refine_nu=ws.nusselt_numbers(b, tprobs),
+                            refine_seconds=round(time.perf_counter() - t0, 1))
         del b
     both = [i for i in range(len(tprobs))
             if out["cold"]["status"][i] == "converged" and out["warm"]["status"][i] == "converged"]
@@ -389,12 +415,39 @@ def warmstart_experiment(args):
         "nu_rel_diff_mean": float(dnu.mean()) if len(both) else None,
         "nu_within_1e-3": int((dnu < 1e-3).sum()),
         "cold_seconds": out["cold"]["seconds"], "warm_seconds": out["warm"]["seconds"],
+        "nu_reference": "the cold start's Nu at the same residual",
         "per_instance": [{"Ra": p["meta"]["Ra"], "Pr": p["meta"]["Pr"], "Qstar": p["meta"]["Qstar"],
                           "cold_steps": out["cold"]["steps"][i], "warm_steps": out["warm"]["steps"][i],
                           "cold_status": out["cold"]["status"][i], "warm_status": out["warm"]["status"][i],
                           "cold_nu": out["cold"]["nu"][i], "warm_nu": out["warm"]["nu"][i]}
                          for i, p in enumerate(tprobs)],
     }
+    if args.ws_refine_tol > 0:
+        rb = [i for i in both if out["cold"]["refine_status"][i] == "converged"
+              and out["warm"]["refine_status"][i] == "converged"]
+        rc = np.array([out["cold"]["refine_nu"][i] for i in rb])
+        rw = np.array([out["warm"]["refine_nu"][i] for i in rb])
+        # the warm start's Nu at 1e-7 against the steady Nu (cold start refined)
+        w7 = np.array([out["warm"]["nu"][i] for i in rb])
+        d_ref = np.abs(rw - rc) / np.abs(rc)
+        d_w7 = np.abs(w7 - rc) / np.abs(rc)
+        d_c7 = np.abs(np.array([out["cold"]["nu"][i] for i in rb]) - rc) / np.abs(rc)
+        res["eval"]["refine"] = {
+            "tol": args.ws_refine_tol, "both_converged": len(rb),
+            "nu_rel_diff_max": float(d_ref.max()) if len(rb) else None,
+            "nu_within_1e-3": int((d_ref < 1e-3).sum()),
+            "warm_at_1e-7_vs_steady_max": float(d_w7.max()) if len(rb) else None,
+            "cold_at_1e-7_vs_steady_max": float(d_c7.max()) if len(rb) else None,
+            "warm_at_1e-7_within_1e-3_of_steady": int((d_w7 < 1e-3).sum()),
+            "cold_at_1e-7_within_1e-3_of_steady": int((d_c7 < 1e-3).sum()),
+            "cold_extra_steps_total": int(sum(out["cold"]["refine_steps"][i] for i in rb)),
+            "warm_extra_steps_total": int(sum(out["warm"]["refine_steps"][i] for i in rb)),
+            "cold_seconds": out["cold"]["refine_seconds"], "warm_seconds": out["warm"]["refine_seconds"],
+        }
+        for i, rec in enumerate(res["eval"]["per_instance"]):
+            rec.update(cold_refined_nu=out["cold"]["refine_nu"][i], warm_refined_nu=out["warm"]["refine_nu"][i],
+                       cold_refine_steps=out["cold"]["refine_steps"][i],
+                       warm_refine_steps=out["warm"]["refine_steps"][i])
     return res
 
 
@@ -430,7 +483,10 @@ def main():
     ap.add_argument("--ws-train-steps", type=int, default=3000)
     ap.add_argument("--ws-eval", type=int, default=64)
     ap.add_argument("--ws-eval-side", type=int, default=512)
-    ap.add_argument("--ws-save", default="")
+    ap.add_argument("--ws-save", default="", help="write the trained parameters (.npy)")
+    ap.add_argument("--ws-load", default="", help="skip data generation and training; load parameters (.npy)")
+    ap.add_argument("--ws-refine-tol", type=float, default=0.0,
+                    help="after the runs to 1e-7, continue both to this residual and compare Nu there")
     ap.add_argument("--ws-out", default="")
     args = ap.parse_args()
 
