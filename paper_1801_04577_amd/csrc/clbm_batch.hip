@@ -330,7 +330,7 @@ clbm_status batch_layout(int n, const clbm_params* p, BatchLayout* L)
     L->buf1.resize(n);
     L->snap.resize(n);
     for (int i = 0; i < n; ++i) {
-        const size_t plane = (size_t)row_pitch(p[i].nx) * p[i].ny;
+        const size_t plane = plane_stride(p[i].nx, p[i].ny);
         L->buf0[i] = take(14 * plane * sizeof(float));
         L->buf1[i] = take(14 * plane * sizeof(float));
         L->snap[i] = take(3 * (size_t)p[i].nx * p[i].ny * sizeof(float));

@@ -66,8 +66,8 @@ __device__ __forceinline__ unsigned mix32(unsigned h)
     return h;
 }
 
-// Flow populations are computed in FP32: stored as is in FP32, and with the dithered
-// rounding (hash of the FP32 bits) in binary16, whose rounding error dominates.
+// Storage of an FP32 value: as is in FP32 (nontemporal), with the unbiased rounding
+// (hash of the FP32 bits) in binary16.
 template <typename S> __device__ __forceinline__ void st(S* p, float v);
 template <> __device__ __forceinline__ void st<float>(float* p, float v) { __builtin_nontemporal_store(v, p); }
 template <> __device__ __forceinline__ void st<__half>(__half* p, float v)

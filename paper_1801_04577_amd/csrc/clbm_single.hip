@@ -53,6 +53,8 @@ clbm_status derive_rates(const clbm_params* p, Rates* r)
 
 int row_pitch(int nx) { return (int)align_up((size_t)nx, kRowAlign); }
 
+size_t plane_stride(int nx, int ny) { return (size_t)row_pitch(nx) * (size_t)ny + kPlaneSkew; }
+
 clbm_status validate(const clbm_params* p, Rates* r)
 {
     if (!p) return CLBM_ERR_INVALID_ARG;
@@ -78,7 +80,7 @@ clbm_status validate(const clbm_params* p, Rates* r)
     if (p->side[0].kind == CLBM_WALL && p->nx < 2) return CLBM_ERR_INVALID_ARG;
     if (p->side[2].kind == CLBM_WALL && p->ny < 2) return CLBM_ERR_INVALID_ARG;
     // 32-bit element offsets inside one 14-plane buffer.
-    const double elems = 14.0 * (double)p->ny * (double)row_pitch(p->nx);
+    const double elems = 14.0 * (double)plane_stride(p->nx, p->ny);
     if (elems >= 4294967295.0) return CLBM_ERR_UNSUPPORTED;
     Rates tmp;
     Rates* rr = r ? r : &tmp;
@@ -98,7 +100,7 @@ LatticeConst make_const(const clbm_params* p, const Rates& r)
     c.nx = p->nx;
     c.ny = p->ny;
     c.pitch = row_pitch(p->nx);
-    c.plane = (unsigned)((size_t)c.pitch * (size_t)p->ny);
+    c.plane = (unsigned)plane_stride(p->nx, p->ny);
     c.periodic_x = p->side[0].kind == CLBM_PERIODIC;
     c.periodic_y = p->side[2].kind == CLBM_PERIODIC;
     const double sp = 0.5 * (r.s_b + r.s_nu), sm = 0.5 * (r.s_b - r.s_nu);
@@ -244,7 +246,7 @@ size_t layout(const clbm_params* p, size_t* buf_bytes, size_t* off_snap, size_t*
               size_t* off_res)
 {
     const size_t elem = p->precision == CLBM_FP16_SHIFTED ? 2 : 4;
-    const size_t plane = (size_t)row_pitch(p->nx) * (size_t)p->ny;
+    const size_t plane = plane_stride(p->nx, p->ny);
     const size_t bb = align_up(14 * plane * elem, kAlign);
     const size_t n = (size_t)p->nx * p->ny;
     size_t off = 2 * bb;

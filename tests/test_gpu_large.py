@@ -56,3 +56,55 @@ def test_fp16_random_lattices(seed):
     e = field_errors(o, s)
     print("fp16s random %d: u %.3e T %.3e" % (seed, e["u"], e["T"]), flush=True)
     assert e["u"] <= 1e-2 and e["T"] <= 1e-2
+
+
+EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_sampled_nodes_after_500_steps(precision):
+    """The benchmark's 4096^2 workload after 500 steps (launch configuration of the
+    benchmark): at 4096 seeded interior nodes, one more GPU step must equal the oracle's
+    collision applied to the populations the GPU streamed into the node (pull of Eq. 11
+    and Eq. 21 from the stored post-collision state). Both sides start from the same
+    stored values, so the differences are the rounding of the result into storage (within
+    2 units in the last place of the stored deviation: FP32 2^-23, FP16 2^-10 relative,
+    plus FP16's subnormal step) and the kernel's relaxation constants, which are rates
+    rounded to FP32 (a relative change of ~6e-8 in the non-equilibrium part, bounded here
+    by 1e-7 of the node's largest deviation; FP16 storage computes in FP32, 1e-6)."""
+    import torch
+    import oracle
+    prob = W.large_cavity(4096)
+    T = f32(W.cavity_initial_T(prob, seed=12345))
+    s = run_gpu(prob, 500, {"T": T}, precision=precision)
+    f0, g0 = s.populations()
+    s.step(1)
+    f1, g1 = s.populations()
+    rng = np.random.default_rng(4096 + precision)
+    xs = rng.integers(1, prob["nx"] - 1, 4096)
+    ys = rng.integers(1, prob["ny"] - 1, 4096)
+    dev = torch.device(f0.device)
+    X = torch.as_tensor(xs, device=dev)
+    Y = torch.as_tensor(ys, device=dev)
+    fin = np.stack([f0[i][Y - int(EY[i]), X - int(EX[i])].cpu().numpy() for i in range(9)], axis=1)
+    gin = np.stack([g0[i][Y - int(EY[i]), X - int(EX[i])].cpu().numpy() for i in range(5)], axis=1)
+    fout = np.stack([f1[i][Y, X].cpu().numpy() for i in range(9)], axis=1).astype(np.float64)
+    gout = np.stack([g1[i][Y, X].cpu().numpy() for i in range(5)], axis=1).astype(np.float64)
+    ulp = 2.0 ** -23 if precision == 0 else 2.0 ** -10
+    floor = 1e-30 if precision == 0 else 2.0 ** -24
+    arith = 1e-7 if precision == 0 else 1e-6
+    worst = 0.0
+    for k in range(len(xs)):
+        fp, gp, _ = oracle.collide(prob, fin[k].astype(np.float64) + W9,
+                                   gin[k].astype(np.float64) + prob["T0"] / 5.0)
+        want_f = fp - W9
+        want_g = gp - prob["T0"] / 5.0
+        for got, want in ((fout[k], want_f), (gout[k], want_g)):
+            bound = 2 * ulp * np.abs(want) + arith * np.abs(want).max() + 2 * floor
+            err = np.abs(got - want) / bound
+            worst = max(worst, float(err.max()))
+    print("4096^2 sampled nodes after 500 steps (%s): worst error / bound = %.3f"
+          % ("fp32" if precision == 0 else "fp16s", worst), flush=True)
+    assert worst <= 1.0
