@@ -52,10 +52,11 @@ template <> __device__ __forceinline__ float ld<float>(const float* p) { return 
 template <> __device__ __forceinline__ float ld<__half>(const __half* p) { return __half2float(*p); }
 
 // Unbiased rounding into storage. x lies between the nearest storable value f and its
-// neighbour g on the other side of x; g is taken with probability |x - f|/|g - f|, the
-// uniform variate being a hash of the bits of x. The expected stored value is x, the
-// decision is a deterministic function of x (runs are reproducible, and a state that
-// no longer changes is stored identically every step).
+// neighbour g on the other side of x; g is taken with probability |x - f|/|g - f|. The
+// uniform variates come from a hash of the bits of the node's results (store_node), so
+// the expected stored value is x and the decision is a deterministic function of the
+// results: runs are reproducible, and a state that no longer changes is stored
+// identically every step.
 __device__ __forceinline__ unsigned mix32(unsigned h)
 {
     h ^= h >> 16;
@@ -66,52 +67,40 @@ __device__ __forceinline__ unsigned mix32(unsigned h)
     return h;
 }
 
-// Storage of an FP32 value: as is in FP32 (nontemporal), with the unbiased rounding
-// (hash of the FP32 bits) in binary16.
-template <typename S> __device__ __forceinline__ void st(S* p, float v);
-template <> __device__ __forceinline__ void st<float>(float* p, float v) { __builtin_nontemporal_store(v, p); }
-template <> __device__ __forceinline__ void st<__half>(__half* p, float v)
-{
-    // Stochastic rounding in the integer domain: binary16 keeps 10 of the 23 fraction bits
-    // of a value with exponent >= -14 and fewer below (its grid spacing is 2^-24 there), so
-    // a hashed offset of as many bits as are dropped is added to the magnitude and those
-    // bits are cleared; the conversion of the result is exact, and the magnitude rounds up
-    // with probability equal to the dropped fraction. Below 2^-24 the two candidates are
-    // 0 and 2^-24.
-    const unsigned u = __float_as_uint(v);
-    const int e = (int)((u >> 23) & 0xffu) - 127;
-    const unsigned h = mix32(u);
-    float w;
-    if (e >= -24) {
-        const int drop = 13 + (e < -14 ? -14 - e : 0);
-        const unsigned mask = (1u << drop) - 1u;
-        w = __uint_as_float((u + (h & mask)) & ~mask);
-    } else {
-        const float a = fabsf(v) * 16777216.f;
-        const float r = (float)(h >> 8) * (1.f / 16777216.f);
-        w = copysignf(r < a ? 5.9604644775390625e-8f : 0.f, v);
-    }
-    *p = __float2half_rn(w);
-}
-
 // Arithmetic type of the collision for a storage type: FP64 for FP32 storage and FP32
 // for binary16 storage (whose rounding, 2^-11, dominates FP32's).
 template <typename S> struct Wide;
 template <> struct Wide<float> { typedef double type; };
 template <> struct Wide<__half> { typedef float type; };
 
-template <typename S> __device__ __forceinline__ void st_dither(S* p, typename Wide<S>::type x);
-// FP64 -> FP32: add a hashed 29-bit offset to the 52-bit mantissa and truncate the 29 bits
+// Bits of a result that feed the node's hash: the low word of an FP64 value (it holds
+// the 29 bits FP32 drops), all bits of an FP32 value.
+__device__ __forceinline__ unsigned hash_bits(double x) { return (unsigned)__double_as_longlong(x); }
+__device__ __forceinline__ unsigned hash_bits(float x) { return __float_as_uint(x); }
+
+// Store x with the unbiased rounding; r is a uniform 32-bit variate.
+template <typename S> __device__ __forceinline__ void st_sr(S* p, typename Wide<S>::type x, unsigned r);
+// FP64 -> FP32: add the top 29 bits of r to the 52-bit mantissa and truncate the 29 bits
 // FP32 does not keep; the conversion of the truncated value is then exact. The magnitude
-// rounds up with probability (discarded bits)/2^29, so the expected stored value is x.
-template <> __device__ __forceinline__ void st_dither<float>(float* p, double x)
+// rounds up with probability (discarded bits)/2^29.
+template <> __device__ __forceinline__ void st_sr<float>(float* p, double x, unsigned r)
 {
     unsigned long long bits = (unsigned long long)__double_as_longlong(x);
-    bits += (unsigned long long)(mix32((unsigned)bits) >> 3);
+    bits += (unsigned long long)(r >> 3);
     bits &= ~0x1FFFFFFFull;
     __builtin_nontemporal_store((float)__longlong_as_double((long long)bits), p);
 }
-template <> __device__ __forceinline__ void st_dither<__half>(__half* p, float x) { st<__half>(p, x); }
+// FP32 -> binary16 with gfx950's stochastic-rounding conversion: the magnitude rounds up
+// with probability equal to the discarded fraction of a binary16 ulp (subnormal spacing
+// 2^-24 included), the random bits taken from the top of r.
+template <> __device__ __forceinline__ void st_sr<__half>(__half* p, float x, unsigned r)
+{
+    typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+    const half2v v = __builtin_amdgcn_cvt_sr_f16_f32(half2v{0, 0}, x, r, false);
+    __half_raw raw;
+    raw.data = v[0];
+    __builtin_nontemporal_store(raw.x, reinterpret_cast<unsigned short*>(p));
+}
 
 struct NodeMacro {
     float drho;   // rho - 1

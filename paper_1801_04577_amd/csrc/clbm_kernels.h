@@ -125,17 +125,25 @@ __device__ __forceinline__ void gather_node(const S* __restrict__ src, const Lat
 }
 
 // Store the post-collision state of one node: the deviations, computed wider than the
-// storage, with the unbiased rounding of st_dither.
+// storage, with the unbiased rounding of st_sr. One hash per node mixes the bits of all
+// 14 results; the k-th store takes h + k * 0x9E3779B9 (a Weyl sequence), each uniform
+// on its own.
 template <typename S>
 __device__ __forceinline__ void store_node(S* __restrict__ dst, const LatticeConst& c, unsigned own,
                                            const typename Wide<S>::type fa[9],
                                            const typename Wide<S>::type tb[5])
 {
     const unsigned P = c.plane;
+    unsigned acc = 0;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) st_dither(dst + i * P + own, fa[i]);
+    for (int i = 0; i < 9; ++i) acc = ((acc << 5) | (acc >> 27)) ^ hash_bits(fa[i]);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) st_dither(dst + (9 + i) * P + own, tb[i]);
+    for (int i = 0; i < 5; ++i) acc = ((acc << 5) | (acc >> 27)) ^ hash_bits(tb[i]);
+    const unsigned h = mix32(acc);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) st_sr(dst + i * P + own, fa[i], h + (unsigned)i * 0x9E3779B9u);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) st_sr(dst + (9 + i) * P + own, tb[i], h + (unsigned)(9 + i) * 0x9E3779B9u);
 }
 
 
