@@ -129,8 +129,10 @@ const char* clbm_status_string(int status);
 clbm_status clbm_derive_rates(const clbm_params* p, double out[7]);
 
 /* Host only. Validates p and returns the workspace size the handle needs: two
- * population buffers (14 planes each, rows padded to 64 elements), a snapshot of
- * (u_x, u_y, T) for the residual, and reduction scratch. */
+ * population buffers, a snapshot of (u_x, u_y, T) for the residual, and reduction
+ * scratch. A population buffer holds each row in blocks of 64 nodes, a block storing
+ * its 14 populations (f_0..f_8, g_0..g_4) 64 values each; rows are padded to whole
+ * blocks. The layout is internal: clbm_populations exports plain planes. */
 clbm_status clbm_workspace_bytes(const clbm_params* p, size_t* bytes);
 
 /* Creates a handle over the caller's workspace (device memory of at least

@@ -29,7 +29,7 @@ __global__ void __launch_bounds__(256) k_init(S* __restrict__ dst, const Lattice
     NodeMacro m;
     if (c.viscous) collide<typename Wide<S>::type, true>(c, a, b, fa, tb, m);
     else collide(c, a, b, fa, tb, m);
-    store_node(dst, c, (unsigned)y * c.pitch + x, fa, tb);
+    store_node(dst, c, node_off(c, x, y), fa, tb);
 }
 
 template <typename S>
@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(256) k_macros(const S* __restrict__ src, const
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     if (x >= c.nx || y >= c.ny) return;
     float a[9], b[5];
-    load_own(src, c, (unsigned)y * c.pitch + x, a, b);
+    load_own(src, c, node_off(c, x, y), a, b);
     const NodeMacro m = c.viscous ? macros_from_post<true>(c, a, b) : macros_from_post(c, a, b);
     const size_t k = (size_t)y * c.nx + x;
     if (rho) rho[k] = 1.f + m.drho;
@@ -57,12 +57,12 @@ __global__ void __launch_bounds__(256) k_populations(const S* __restrict__ src, 
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     if (x >= c.nx || y >= c.ny) return;
-    const unsigned own = (unsigned)y * c.pitch + x;
+    const unsigned own = node_off(c, x, y);
     const size_t n = (size_t)c.nx * c.ny, k = (size_t)y * c.nx + x;
     if (f)
-        for (int i = 0; i < 9; ++i) f[i * n + k] = ld(src + (size_t)i * c.plane + own);
+        for (int i = 0; i < 9; ++i) f[i * n + k] = ld(src + i * kBlock + own);
     if (g)
-        for (int i = 0; i < 5; ++i) g[i * n + k] = ld(src + (size_t)(9 + i) * c.plane + own);
+        for (int i = 0; i < 5; ++i) g[i * n + k] = ld(src + (9 + i) * kBlock + own);
 }
 
 // Diagnostics. Per node: rho - 1, |u|^2, |u - u_snap|^2, T^2, (T - T_snap)^2, NaN flag;
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag(const S* __restrict__ src, 
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
         const int y = (int)(k / c.nx), x = (int)(k - (size_t)y * c.nx);
-        const unsigned own = (unsigned)y * c.pitch + x;
+        const unsigned own = node_off(c, x, y);
         float a[9], b[5];
         load_own(src, c, own, a, b);
         const NodeMacro m = c.viscous ? macros_from_post<true>(c, a, b) : macros_from_post(c, a, b);
@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag(const S* __restrict__ src, 
             if (!wall[s]) continue;
             const int x2 = s == 0 ? x + 1 : (s == 1 ? x - 1 : x);
             const int y2 = s == 2 ? y + 1 : (s == 3 ? y - 1 : y);
-            const unsigned o2 = (unsigned)y2 * c.pitch + x2;
+            const unsigned o2 = node_off(c, x2, y2);
             const float th2 = c.viscous ? theta_post<S, true>(src, c, o2) : theta_post<S, false>(src, c, o2);
             const float thw = c.a1[s] * m.theta + c.a2[s] * th2 + c.a3[s];
             acc[5 + s] += (8.0 * thw - 9.0 * m.theta + th2) / 3.0;

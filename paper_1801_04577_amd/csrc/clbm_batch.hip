@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(1024) k_batch_step(const BatchInst* __restrict
                 gather_node(src, c, x, y, a, b);
                 collide(c, a, b, fa, tb, m);
             }
-            store_node(dst, c, (unsigned)y * c.pitch + x, fa, tb);
+            store_node(dst, c, node_off(c, x, y), fa, tb);
         }
     }
 }
@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(1024) k_batch_diag(const BatchInst* __restrict
             const float* src = reinterpret_cast<const float*>(I.buf[parity]);
             float* snap = reinterpret_cast<float*>(I.snap);
             float a[9], b[5];
-            load_own(src, c, (unsigned)y * c.pitch + x, a, b);
+            load_own(src, c, node_off(c, x, y), a, b);
             const NodeMacro m = c.viscous ? macros_from_post<true>(c, a, b) : macros_from_post(c, a, b);
             const float T = c.T0 + m.theta;
             const size_t k = (size_t)y * c.nx + x, np = (size_t)c.nx * c.ny;
@@ -330,9 +330,9 @@ clbm_status batch_layout(int n, const clbm_params* p, BatchLayout* L)
     L->buf1.resize(n);
     L->snap.resize(n);
     for (int i = 0; i < n; ++i) {
-        const size_t plane = plane_stride(p[i].nx, p[i].ny);
-        L->buf0[i] = take(14 * plane * sizeof(float));
-        L->buf1[i] = take(14 * plane * sizeof(float));
+        const size_t elems = buffer_elems(p[i].nx, p[i].ny);
+        L->buf0[i] = take(elems * sizeof(float));
+        L->buf1[i] = take(elems * sizeof(float));
         L->snap[i] = take(3 * (size_t)p[i].nx * p[i].ny * sizeof(float));
     }
     L->total = off;

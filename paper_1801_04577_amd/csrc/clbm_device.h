@@ -26,10 +26,17 @@ __host__ __device__ constexpr float wgt(int i) { return i == 0 ? 4.f / 9.f : (i 
 
 constexpr float CT2 = 0.4f;  // c_T^2 (Sec. 3)
 
+// Storage layout of a population buffer: each row is cut into blocks of kBlock nodes,
+// and a block stores its 14 populations one after the other, kBlock values each
+// ([y][x / kBlock][i][x % kBlock]). A wave of 64 lanes then reads and writes 14
+// contiguous 256-byte (FP32) segments instead of touching 14 planes a buffer apart.
+constexpr unsigned kBlock = 64;
+constexpr unsigned kBlockElems = 14 * kBlock;
+
 // Per-lattice constants of one step, passed by value to every kernel.
 struct LatticeConst {
-    int nx, ny, pitch;         // pitch: elements per stored row (multiple of 64)
-    unsigned plane;            // elements per population plane = ny * pitch
+    int nx, ny;
+    unsigned rowlen;           // elements per stored row: ceil(nx / kBlock) * kBlockElems
     int periodic_x, periodic_y;
     int moving;                // any wall with u_wall != 0
     float one_m_sp, sm;        // 1 - s_plus, s_minus  (Eq. 8 block on k20, k02)
@@ -45,6 +52,12 @@ struct LatticeConst {
     float uw[4];               // tangential wall speeds, side order x-, x+, y-, y+
     float a1[4], a2[4], a3[4]; // theta_w = a1 theta_1 + a2 theta_2 + a3  (Eq. 28 in theta = T - T0)
 };
+
+// Element offset of population 0 of node (x, y); population i is kBlock * i further.
+__device__ __forceinline__ unsigned node_off(const LatticeConst& c, int x, int y)
+{
+    return (unsigned)y * c.rowlen + ((unsigned)x / kBlock) * kBlockElems + ((unsigned)x % kBlock);
+}
 
 // Storage loads: float32 or binary16.
 template <typename S> __device__ __forceinline__ float ld(const S* p);

@@ -23,8 +23,6 @@ namespace clbm {
 
 void set_last_hip_error(hipError_t e, const char* what, const char* file, int line);
 
-constexpr int kRowAlign = 64;    // stored row pitch, in elements
-constexpr int kPlaneSkew = 0;    // elements added to each population plane's stride
 constexpr size_t kAlign = 256;   // workspace region alignment, bytes
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -40,9 +38,9 @@ clbm_status derive_rates(const clbm_params* p, Rates* r);
 clbm_status validate(const clbm_params* p, Rates* r);
 // Kernel constant block for a validated parameter block.
 LatticeConst make_const(const clbm_params* p, const Rates& r);
-int row_pitch(int nx);
-// Elements between consecutive population planes: ny rows of row_pitch(nx), plus
-// kPlaneSkew.
-size_t plane_stride(int nx, int ny);
+// Elements of one stored row (ceil(nx / kBlock) blocks of 14 populations) and of one
+// population buffer (ny rows).
+size_t row_elems(int nx);
+size_t buffer_elems(int nx, int ny);
 
 }  // namespace clbm

@@ -4,8 +4,9 @@
 // that stream into the node (Eq. 11, Eq. 21), substitutes the wall links
 // (half-way bounce-back for f, Sec. 3; general bounce-back for g, Eq. 26-28),
 // collides (clbm_device.h) and stores the 14 post-collision populations at its
-// own address in the other buffer. Populations are structure-of-arrays planes
-// [i][ny][pitch]; flow planes 0..8 then temperature planes 9..13.
+// own address in the other buffer. Storage is block-interleaved (clbm_device.h):
+// population i of node (x, y) sits at node_off(x, y) + i * kBlock, flow populations
+// 0..8 then temperature populations 9..13.
 #pragma once
 
 #include "clbm_device.h"
@@ -17,20 +18,20 @@ template <typename S>
 __device__ __forceinline__ void load_own(const S* __restrict__ src, const LatticeConst& c,
                                          unsigned own, float a[9], float b[5])
 {
-    const unsigned P = c.plane;
+    constexpr unsigned P = kBlock;
 #pragma unroll
     for (int i = 0; i < 9; ++i) a[i] = ld(src + i * P + own);
 #pragma unroll
     for (int i = 0; i < 5; ++i) b[i] = ld(src + (9 + i) * P + own);
 }
 
-// T - T0 at time t of the node at element offset off, from its stored post-collision
+// T - T0 at time t of the node at element offset off (node_off), from its stored post-collision
 // populations: sum g* - Q/2, with Q the node's own source under VH.
 template <typename S, bool VH>
 __device__ __forceinline__ float theta_post(const S* __restrict__ src, const LatticeConst& c,
                                             unsigned off)
 {
-    const unsigned P = c.plane;
+    constexpr unsigned P = kBlock;
     const S* gs = src + 9 * P;
     if constexpr (VH) {
         float a[9], b[5];
@@ -51,8 +52,8 @@ template <typename S, bool VH = false>
 __device__ __forceinline__ void gather_node(const S* __restrict__ src, const LatticeConst& c, int x,
                                             int y, float a[9], float b[5])
 {
-    const int nx = c.nx, ny = c.ny, pitch = c.pitch;
-    const unsigned P = c.plane;
+    const int nx = c.nx, ny = c.ny;
+    constexpr unsigned P = kBlock;
     // Source coordinates of the links; a link whose source lies outside a wall is
     // flagged and its source clamped to the node itself (the address is never used).
     int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
@@ -61,27 +62,30 @@ __device__ __forceinline__ void gather_node(const S* __restrict__ src, const Lat
     if (xp >= nx) { if (c.periodic_x) xp = 0; else { oxp = true; xp = x; } }
     if (ym < 0) { if (c.periodic_y) ym = ny - 1; else { oym = true; ym = y; } }
     if (yp >= ny) { if (c.periodic_y) yp = 0; else { oyp = true; yp = y; } }
-    const unsigned rC = (unsigned)y * pitch, rM = (unsigned)ym * pitch, rP = (unsigned)yp * pitch;
-    const unsigned own = rC + x;
+    // Offsets of the three source rows and the three source columns (node_off split).
+    const unsigned rC = (unsigned)y * c.rowlen, rM = (unsigned)ym * c.rowlen, rP = (unsigned)yp * c.rowlen;
+    auto col = [](int xx) { return ((unsigned)xx / kBlock) * kBlockElems + ((unsigned)xx % kBlock); };
+    const unsigned cM = col(xm), cC = col(x), cP = col(xp);
+    const unsigned own = rC + cC;
 
     // Eq. (11) pull form f_i(x, t+1) = f_i*(x - e_i, t); a wall link takes the
     // opposite population of the node itself (half-way bounce-back).
     a[0] = ld(src + own);
-    a[1] = ld(src + (oxm ? 3 * P + own : 1 * P + rC + xm));
-    a[2] = ld(src + (oym ? 4 * P + own : 2 * P + rM + x));
-    a[3] = ld(src + (oxp ? 1 * P + own : 3 * P + rC + xp));
-    a[4] = ld(src + (oyp ? 2 * P + own : 4 * P + rP + x));
-    a[5] = ld(src + ((oxm | oym) ? 7 * P + own : 5 * P + rM + xm));
-    a[6] = ld(src + ((oxp | oym) ? 8 * P + own : 6 * P + rM + xp));
-    a[7] = ld(src + ((oxp | oyp) ? 5 * P + own : 7 * P + rP + xp));
-    a[8] = ld(src + ((oxm | oyp) ? 6 * P + own : 8 * P + rP + xm));
+    a[1] = ld(src + (oxm ? 3 * P + own : 1 * P + rC + cM));
+    a[2] = ld(src + (oym ? 4 * P + own : 2 * P + rM + cC));
+    a[3] = ld(src + (oxp ? 1 * P + own : 3 * P + rC + cP));
+    a[4] = ld(src + (oyp ? 2 * P + own : 4 * P + rP + cC));
+    a[5] = ld(src + ((oxm | oym) ? 7 * P + own : 5 * P + rM + cM));
+    a[6] = ld(src + ((oxp | oym) ? 8 * P + own : 6 * P + rM + cP));
+    a[7] = ld(src + ((oxp | oyp) ? 5 * P + own : 7 * P + rP + cP));
+    a[8] = ld(src + ((oxm | oyp) ? 6 * P + own : 8 * P + rP + cM));
     // Eq. (21); a wall link loads the opposite population of the node, completed below.
     const S* gs = src + 9 * P;
     b[0] = ld(gs + own);
-    b[1] = ld(gs + (oxm ? 3 * P + own : 1 * P + rC + xm));
-    b[2] = ld(gs + (oym ? 4 * P + own : 2 * P + rM + x));
-    b[3] = ld(gs + (oxp ? 1 * P + own : 3 * P + rC + xp));
-    b[4] = ld(gs + (oyp ? 2 * P + own : 4 * P + rP + x));
+    b[1] = ld(gs + (oxm ? 3 * P + own : 1 * P + rC + cM));
+    b[2] = ld(gs + (oym ? 4 * P + own : 2 * P + rM + cC));
+    b[3] = ld(gs + (oxp ? 1 * P + own : 3 * P + rC + cP));
+    b[4] = ld(gs + (oyp ? 2 * P + own : 4 * P + rP + cC));
 
     if (oxm | oxp | oym | oyp) {
         // Eq. (26): g_i(x_f, t+1) = -g*_opp(i)(x_f, t) + c_T^2 T_w, with T_w from Eq. (28)
@@ -90,19 +94,19 @@ __device__ __forceinline__ void gather_node(const S* __restrict__ src, const Lat
         auto theta_at = [&](unsigned off) { return theta_post<S, VH>(src, c, off); };
         const float th1 = theta_at(own);
         if (oxm) {
-            const float tw = c.a1[0] * th1 + c.a2[0] * theta_at(rC + x + 1) + c.a3[0];
+            const float tw = c.a1[0] * th1 + c.a2[0] * theta_at(node_off(c, x + 1, y)) + c.a3[0];
             b[1] = -b[1] + CT2 * tw;
         }
         if (oxp) {
-            const float tw = c.a1[1] * th1 + c.a2[1] * theta_at(rC + x - 1) + c.a3[1];
+            const float tw = c.a1[1] * th1 + c.a2[1] * theta_at(node_off(c, x - 1, y)) + c.a3[1];
             b[3] = -b[3] + CT2 * tw;
         }
         if (oym) {
-            const float tw = c.a1[2] * th1 + c.a2[2] * theta_at(rC + pitch + x) + c.a3[2];
+            const float tw = c.a1[2] * th1 + c.a2[2] * theta_at(own + c.rowlen) + c.a3[2];
             b[2] = -b[2] + CT2 * tw;
         }
         if (oyp) {
-            const float tw = c.a1[3] * th1 + c.a2[3] * theta_at(rC - pitch + x) + c.a3[3];
+            const float tw = c.a1[3] * th1 + c.a2[3] * theta_at(own - c.rowlen) + c.a3[3];
             b[4] = -b[4] + CT2 * tw;
         }
         if (c.moving) {
@@ -133,7 +137,7 @@ __device__ __forceinline__ void store_node(S* __restrict__ dst, const LatticeCon
                                            const typename Wide<S>::type fa[9],
                                            const typename Wide<S>::type tb[5])
 {
-    const unsigned P = c.plane;
+    constexpr unsigned P = kBlock;
     unsigned acc = 0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) acc = ((acc << 5) | (acc >> 27)) ^ hash_bits(fa[i]);
@@ -178,7 +182,7 @@ __global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __r
             gather_node<S, VH>(src, c, x, y, a, b);
             NodeMacro m;
             collide<typename Wide<S>::type, VH>(c, a, b, fa, tb, m);
-            store_node(dst, c, (unsigned)y * c.pitch + x, fa, tb);
+            store_node(dst, c, node_off(c, x, y), fa, tb);
         }
     }
 }

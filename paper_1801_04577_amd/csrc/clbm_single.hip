@@ -51,9 +51,9 @@ clbm_status derive_rates(const clbm_params* p, Rates* r)
     return CLBM_OK;
 }
 
-int row_pitch(int nx) { return (int)align_up((size_t)nx, kRowAlign); }
+size_t row_elems(int nx) { return ((size_t)nx + kBlock - 1) / kBlock * kBlockElems; }
 
-size_t plane_stride(int nx, int ny) { return (size_t)row_pitch(nx) * (size_t)ny + kPlaneSkew; }
+size_t buffer_elems(int nx, int ny) { return row_elems(nx) * (size_t)ny; }
 
 clbm_status validate(const clbm_params* p, Rates* r)
 {
@@ -79,8 +79,8 @@ clbm_status validate(const clbm_params* p, Rates* r)
     // Eq. (27) needs a second layer of nodes next to each wall.
     if (p->side[0].kind == CLBM_WALL && p->nx < 2) return CLBM_ERR_INVALID_ARG;
     if (p->side[2].kind == CLBM_WALL && p->ny < 2) return CLBM_ERR_INVALID_ARG;
-    // 32-bit element offsets inside one 14-plane buffer.
-    const double elems = 14.0 * (double)plane_stride(p->nx, p->ny);
+    // 32-bit element offsets inside one population buffer.
+    const double elems = (double)buffer_elems(p->nx, p->ny);
     if (elems >= 4294967295.0) return CLBM_ERR_UNSUPPORTED;
     Rates tmp;
     Rates* rr = r ? r : &tmp;
@@ -99,8 +99,7 @@ LatticeConst make_const(const clbm_params* p, const Rates& r)
     std::memset(&c, 0, sizeof c);
     c.nx = p->nx;
     c.ny = p->ny;
-    c.pitch = row_pitch(p->nx);
-    c.plane = (unsigned)plane_stride(p->nx, p->ny);
+    c.rowlen = (unsigned)row_elems(p->nx);
     c.periodic_x = p->side[0].kind == CLBM_PERIODIC;
     c.periodic_y = p->side[2].kind == CLBM_PERIODIC;
     const double sp = 0.5 * (r.s_b + r.s_nu), sm = 0.5 * (r.s_b - r.s_nu);
@@ -226,7 +225,7 @@ struct clbm_handle {
     LatticeConst c;
     hipStream_t stream;
     int elem;            // bytes per stored population
-    size_t buf_bytes;    // bytes of one 14-plane buffer
+    size_t buf_bytes;    // bytes of one population buffer (14 populations per node)
     void* buf[2];
     float* snap;         // (u_x, u_y, T), 3 dense planes
     double* partial;     // kDiagMaxBlocks x kDiagSums
@@ -246,8 +245,7 @@ size_t layout(const clbm_params* p, size_t* buf_bytes, size_t* off_snap, size_t*
               size_t* off_res)
 {
     const size_t elem = p->precision == CLBM_FP16_SHIFTED ? 2 : 4;
-    const size_t plane = plane_stride(p->nx, p->ny);
-    const size_t bb = align_up(14 * plane * elem, kAlign);
+    const size_t bb = align_up(buffer_elems(p->nx, p->ny) * elem, kAlign);
     const size_t n = (size_t)p->nx * p->ny;
     size_t off = 2 * bb;
     const size_t snap = off;

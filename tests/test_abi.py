@@ -62,7 +62,7 @@ def test_rates_match_oracle(L, k):
 def test_workspace_and_validation(L):
     p = clbm.make_params(W.channel())
     n = clbm.clbm_workspace_bytes(p)
-    # two 14-plane FP32 buffers with rows padded to 64 elements, plus scratch
+    # two FP32 population buffers (14 values per node, rows padded to 64 nodes), plus scratch
     assert n >= 2 * 14 * 64 * 32 * 4
     p16 = clbm.make_params(W.channel(), clbm.CLBM_FP16_SHIFTED)
     assert clbm.clbm_workspace_bytes(p16) < n
