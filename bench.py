@@ -108,7 +108,7 @@ def measured_traffic(precision, n):
     return prof.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(prob, target_s=12.0):
+def cpu_baseline(prob, target_s=15.0):
     """The FP64 oracle on a 256-row strip of the same lattice and parameters, all host
     threads, steps chosen so the sample takes about target_s seconds."""
     import numpy as np
@@ -116,9 +116,10 @@ def cpu_baseline(prob, target_s=12.0):
     strip = dict(prob, ny=256)
     nth = oracle.default_threads()
     o = oracle.Sim(strip, nthreads=nth)
+    o.step(1)                      # first step: thread start-up
     t0 = time.perf_counter()
-    o.step(1)
-    dt1 = time.perf_counter() - t0
+    o.step(4)
+    dt1 = (time.perf_counter() - t0) / 4
     nsteps = max(1, int(target_s / max(dt1, 1e-3)))
     t0 = time.perf_counter()
     o.step(nsteps)

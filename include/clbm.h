@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define CLBM_ABI_VERSION 2
+#define CLBM_ABI_VERSION 3
 
 typedef enum {
     CLBM_OK = 0,
@@ -116,6 +116,10 @@ typedef struct {
     double res_T;     /* sqrt(sum_dT2/sum_T2)/K, same convention */
     double dTdn[4];   /* per side: mean outward normal derivative of T at the wall (Eq. 27) */
     double T_wall[4]; /* per side: mean wall temperature (Eq. 28) */
+    double wall_flux[4]; /* per side: mean heat leaving the fluid through the wall per wall
+                            node and step, 2 g*_out - c_T^2 T_w of the link that crosses it
+                            (Eq. 26); equals -alpha dT/dn up to the discretisation error,
+                            a cross-check of dTdn */
     long nan_count;   /* nodes with a non-finite rho, u or T */
 } clbm_diag;
 

@@ -66,10 +66,11 @@ __global__ void __launch_bounds__(256) k_populations(const S* __restrict__ src, 
 }
 
 // Diagnostics. Per node: rho - 1, |u|^2, |u - u_snap|^2, T^2, (T - T_snap)^2, NaN flag;
-// per wall node: outward dT/dn (Eq. 27) and T_w (Eq. 28). Sums in FP64: wave64
+// per wall node: outward dT/dn (Eq. 27), T_w (Eq. 28) and the heat flux of the
+// bounced link. Sums in FP64: wave64
 // shuffles, then LDS across the waves of the workgroup, then one partial per
 // workgroup; k_diag_final adds the partials in a fixed order.
-constexpr int kDiagSums = 15;  // drho, u2, du2, T2, dT2, dTdn[4], Tw[4], nan, count
+constexpr int kDiagSums = 19;  // drho, u2, du2, T2, dT2, dTdn[4], Tw[4], nan, count, flux[4]
 constexpr int kDiagBlock = 256;
 constexpr int kDiagMaxBlocks = 1024;
 
@@ -123,6 +124,10 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag(const S* __restrict__ src, 
             const float thw = c.a1[s] * m.theta + c.a2[s] * th2 + c.a3[s];
             acc[5 + s] += (8.0 * thw - 9.0 * m.theta + th2) / 3.0;
             acc[9 + s] += (double)c.T0 + thw;
+            // Heat carried through the wall by the link that crosses it (Eq. 26): g*
+            // leaves, -g* + c_T^2 T_w comes back, a net 2 g* - c_T^2 T_w per step.
+            const float gout = b[s == 0 ? 3 : (s == 1 ? 1 : (s == 2 ? 4 : 2))] + 0.2f * c.T0;
+            acc[15 + s] += 2.0 * gout - 0.4 * ((double)c.T0 + thw);
         }
         acc[14] += 1.0;
     }

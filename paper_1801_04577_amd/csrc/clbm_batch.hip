@@ -660,6 +660,7 @@ clbm_status clbm_batch_diagnostics(clbm_batch* b, int i, clbm_diag* out)
         if (p.side[s].kind != CLBM_WALL) continue;
         out->dTdn[s] = r[5 + s] / len[s];
         out->T_wall[s] = r[9 + s] / len[s];
+        out->wall_flux[s] = r[15 + s] / len[s];
     }
     out->nan_count = (long)r[13];
     return out->nan_count > 0 ? CLBM_ERR_NAN : CLBM_OK;

@@ -525,6 +525,7 @@ clbm_status clbm_diagnostics(clbm_handle* h, clbm_diag* out)
         if (h->p.side[s].kind != CLBM_WALL) continue;
         out->dTdn[s] = r[5 + s] / len[s];
         out->T_wall[s] = r[9 + s] / len[s];
+        out->wall_flux[s] = r[15 + s] / len[s];
     }
     out->nan_count = (long)r[13];
     h->snap_step = h->step;

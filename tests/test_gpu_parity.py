@@ -143,6 +143,14 @@ def test_diagnostics_match_oracle():
     for side, (Tw, dTdn) in enumerate(walls):
         assert abs(d.dTdn[side] - dTdn.mean()) <= 1e-4 * scale, side
         assert d.T_wall[side] == pytest.approx(Tw.mean(), abs=1e-5)
+    # heat carried by the bounced links, 2 g*_out - c_T^2 T_w (Eq. 26), from the oracle's
+    # post-collision populations at the wall nodes
+    _, g = o.post_collision()
+    g_out = [g[:, 0, 3], g[:, -1, 1], g[0, :, 4], g[-1, :, 2]]
+    flux = [float(np.mean(2.0 * go - 0.4 * Tw)) for go, (Tw, _) in zip(g_out, walls)]
+    fscale = max(abs(v) for v in flux)
+    for side in range(4):
+        assert abs(d.wall_flux[side] - flux[side]) <= 1e-4 * fscale, (side, d.wall_flux[side], flux[side])
     # residual: the snapshot is the state of the previous call
     s.step(100)
     d2 = s.diagnostics()

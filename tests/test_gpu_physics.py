@@ -70,7 +70,8 @@ def table1_quantities(s, d, prob):
     dT = prob["sides"][0]["b3"] - prob["sides"][1]["b3"]
     return {"u_max": umax * H / alpha, "y_max": ypos / H, "v_max": vmax * H / alpha,
             "x_max": xpos / H, "Nu": clbm.nusselt(d, 1, H, dT, into_wall=True),
-            "Nu_hot": clbm.nusselt(d, 0, H, dT, into_wall=False)}
+            "Nu_hot": clbm.nusselt(d, 0, H, dT, into_wall=False),
+            "Nu_flux": clbm.nusselt_flux(d, 1, H, dT, alpha, into_wall=True)}
 
 
 @pytest.mark.parametrize("k", [0, 1, 2, 3])
@@ -83,6 +84,8 @@ def test_table1(k):
     print("Ra %.0e on %d^2 after %d steps: %s" % (Ra, n, s.t, q), flush=True)
     assert q["Nu"] == pytest.approx(g["Nu"][k], rel=1e-2)
     assert q["Nu_hot"] == pytest.approx(q["Nu"], rel=1e-3)   # energy balance at steady state
+    # the heat carried by the bounced links agrees with the wall gradient of Eq. (27)
+    assert q["Nu_flux"] == pytest.approx(q["Nu"], rel=5e-3)
     assert q["u_max"] == pytest.approx(g["u_max"][k], rel=1e-2)
     assert q["v_max"] == pytest.approx(g["v_max"][k], rel=2e-2)
     assert abs(q["y_max"] - g["y_max"][k]) <= 1.5 / n
@@ -123,3 +126,24 @@ def test_lambda2_sweep_batched(alpha, best):
     assert grid[k] == pytest.approx(best, abs=1e-12)
     assert errs[k] < 1e-6
     assert sorted(errs)[1] > 1e-5
+
+
+@pytest.mark.parametrize("alpha", [0.1, 1.0 / 3.0])
+def test_wall_flux_closed_form(alpha):
+    """Sec. 3.1 source problem at steady state: all the heat Q L produced in a column
+    leaves through the bottom wall (T = 0) and none through the top (T' = 0 there), so
+    both the bounced-link flux and -alpha dT/dn of Eq. (27) equal Q L at the bottom and
+    vanish at the top (Eq. 27 is exact for the quadratic profile)."""
+    import paper_1801_04577_amd as clbm
+    L = 6
+    prob = W.diffusion_source(alpha, W.dirichlet(0.0), W.dirichlet(1.0), L=L)
+    s = clbm.Solver(prob)
+    s.init()
+    s.step(20000)
+    d = s.diagnostics()
+    QL = prob["Q"] * L
+    print("alpha %.4f: bottom flux %.8e grad %.8e (Q L %.8e), top flux %.2e grad %.2e"
+          % (alpha, d.wall_flux[2], -alpha * d.dTdn[2], QL, d.wall_flux[3], -alpha * d.dTdn[3]), flush=True)
+    assert d.wall_flux[2] == pytest.approx(QL, rel=1e-5)
+    assert -alpha * d.dTdn[2] == pytest.approx(QL, rel=1e-5)
+    assert abs(d.wall_flux[3]) <= 1e-5 * QL and abs(alpha * d.dTdn[3]) <= 1e-5 * QL
