@@ -47,16 +47,18 @@ def time_steps(torch, s, steps, diag_every):
 
 
 def kernel_avg_ms(torch, s, launches):
-    """Average duration of one fused-step launch: HIP events on the solver's stream
-    around `launches` back-to-back launches."""
+    """Average duration of one launch of the step kernel (one or two time steps per
+    launch): HIP events on the solver's stream around `launches` back-to-back launches.
+    Returns (ms per launch, steps per launch)."""
+    spl = s.get_launch()["steps_per_launch"]
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(s.stream)
-    s.step(launches)
+    s.step(launches * spl)
     e1.record(s.stream)
     e1.synchronize()
-    return e0.elapsed_time(e1) / launches
+    return e0.elapsed_time(e1) / launches, spl
 
 
 def copy_ceiling(torch, clbm, nbytes=2 << 30, reps=10):
@@ -94,16 +96,16 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision, n):
+def measured_traffic(precision, n, steps_per_launch):
     """HBM bytes per step-kernel launch from the committed counter profile (FETCH_SIZE and
     WRITE_SIZE scaled by the same counters on the reference copy), or None when there is
-    no profile for this kernel source and workload."""
+    no profile for this kernel source, workload and launch mode."""
     path = os.path.join(ROOT, "profiles", "step_cavity%d_%s_hbm_traffic.json" % (n, precision))
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         prof = json.load(fh)
-    if prof.get("source_digest") != source_digest():
+    if prof.get("source_digest") != source_digest() or prof.get("steps_per_launch", 1) != steps_per_launch:
         return None
     return prof.get("traffic_bytes_per_launch")
 
@@ -156,7 +158,10 @@ def summarize_profiles(trace_db, fetch_db, write_db, precision, n, command):
             per.setdefault(short(kname), []).append((grid, val))
         counters[cname] = per
     copy_name = [k for k in counters["FETCH_SIZE"] if "k_stream_copy" in k][0]
-    step_name = [k for k in counters["FETCH_SIZE"] if "k_step" in k][0]
+    # the two-step kernel when the run used it, else the single-step one
+    names = sorted((k for k in counters["FETCH_SIZE"] if "k_step" in k), key=lambda k: "k_step2" not in k)
+    step_name = names[0]
+    spl = 2 if "k_step2" in step_name else 1
     copy_bytes = 2 << 30  # bench.py's reference copy: 2 GiB read and 2 GiB written per launch
     f_copy = statistics.mean(v for _, v in counters["FETCH_SIZE"][copy_name])
     w_copy = statistics.mean(v for _, v in counters["WRITE_SIZE"][copy_name])
@@ -164,11 +169,12 @@ def summarize_profiles(trace_db, fetch_db, write_db, precision, n, command):
     w_step = statistics.mean(v for _, v in counters["WRITE_SIZE"][step_name])
     sf, sw = copy_bytes / 1024 / f_copy, copy_bytes / 1024 / w_copy
     traffic = (f_step * sf + w_step * sw) * 1024
-    alg = BYTES_PER_LUP[precision] * n * n
+    alg = BYTES_PER_LUP[precision] * n * n * spl
     tag = "step_cavity%d_%s" % (n, precision)
-    step_row = [r for r in top if "k_step" in r[0]][0]
+    step_row = [r for r in top if short(r[0]) == step_name][0]
     prof = {
-        "kernel": step_name, "workload": "cavity %dx%d Ra=1e6 Pr=0.71 Q=5e-6, %s" % (n, n, precision),
+        "kernel": step_name, "steps_per_launch": spl,
+        "workload": "cavity %dx%d Ra=1e6 Pr=0.71 Q=5e-6, %s" % (n, n, precision),
         "source_digest": source_digest(),
         "fetch_kib_per_dispatch": f_step, "write_kib_per_dispatch": w_step,
         "copy_fetch_kib_per_dispatch": f_copy, "copy_write_kib_per_dispatch": w_copy,
@@ -197,7 +203,8 @@ def summarize_profiles(trace_db, fetch_db, write_db, precision, n, command):
               "| WRITE_SIZE, reference copy of 2 GiB (KiB/dispatch) | %.1f |" % w_copy,
               "| scale factors (known bytes / counter) | fetch %.4f, write %.4f |" % (sf, sw),
               "| traffic per launch (bytes) | %.4e |" % traffic,
-              "| algorithmic bytes per launch (%d B x %d nodes) | %.4e |" % (BYTES_PER_LUP[precision], n * n, alg),
+              "| algorithmic bytes per launch (%d B x %d nodes x %d step(s)) | %.4e |"
+              % (BYTES_PER_LUP[precision], n * n, spl, alg),
               "| traffic / algorithmic | %.4f |" % (traffic / alg),
               "", "Step-kernel source digest: %s" % prof["source_digest"]]
     with open(os.path.join(ROOT, "profiles", tag + "_rocprof.md"), "w") as fh:
@@ -466,7 +473,7 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "fp16s"], default="fp32")
     ap.add_argument("--diag-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--launch", default="", help="block_x,block_y,rows,remap")
+    ap.add_argument("--launch", default="", help="block_x,block_y,rows,remap[,steps_per_launch]")
     ap.add_argument("--kernel-launches", type=int, default=200)
     ap.add_argument("--batched", action="store_true", help="run the batched-sweep benchmark only")
     ap.add_argument("--sweep-count", type=int, default=256)
@@ -518,8 +525,8 @@ def main():
     prec = clbm.CLBM_FP16_SHIFTED if args.precision == "fp16s" else clbm.CLBM_FP32
     s = clbm.Solver(prob, prec)
     if args.launch:
-        bx, by, rows, remap = [int(v) for v in args.launch.split(",")]
-        s.set_launch(bx, by, rows, remap)
+        v = [int(x) for x in args.launch.split(",")]
+        s.set_launch(*v)
     T0 = torch.from_numpy(W.cavity_initial_T(prob, seed=12345).astype(np.float32))
     s.init(T=T0)
     log("bench: %dx%d %s, warmup %d" % (args.n, args.n, args.precision, args.warmup))
@@ -529,11 +536,12 @@ def main():
     nodes = args.n * args.n
     mlups = nodes * args.steps / wall / 1e6
     log("bench: %.3f ms/step, %.1f MLUPS" % (wall / args.steps * 1e3, mlups))
-    kms = kernel_avg_ms(torch, s, args.kernel_launches)
+    kms, spl = kernel_avg_ms(torch, s, args.kernel_launches)
     d = s.diagnostics()
     bpl = BYTES_PER_LUP[args.precision]
-    achieved = bpl * nodes / (kms * 1e-3) / 1e9
-    log("bench: step kernel %.4f ms avg, %.0f GB/s, nan %d" % (kms, achieved, d.nan_count))
+    achieved = bpl * nodes * spl / (kms * 1e-3) / 1e9
+    log("bench: step kernel %.4f ms avg per launch of %d step(s), %.0f GB/s algorithmic, nan %d"
+        % (kms, spl, achieved, d.nan_count))
     copy_gbs, copy_ms = copy_ceiling(torch, clbm)
     log("bench: reference copy %.0f GB/s" % copy_gbs)
 
@@ -550,9 +558,10 @@ def main():
                    "launch": s.get_launch()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.precision, args.n),
-                     "algorithmic_bytes_per_launch": bpl * nodes,
-                     "kernel": "k_step", "kernel_avg_ms": round(kms, 5), "bytes_per_lup": bpl,
+                     "traffic": measured_traffic(args.precision, args.n, spl),
+                     "algorithmic_bytes_per_launch": bpl * nodes * spl,
+                     "kernel": "k_step2" if spl == 2 else "k_step", "steps_per_launch": spl,
+                     "kernel_avg_ms": round(kms, 5), "bytes_per_lup": bpl,
                      "copy_ceiling_GBs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
     }

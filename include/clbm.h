@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define CLBM_ABI_VERSION 3
+#define CLBM_ABI_VERSION 4
 
 typedef enum {
     CLBM_OK = 0,
@@ -96,11 +96,18 @@ typedef struct {
 } clbm_params;
 
 /* Kernel launch shape of the fused step (set by the autotuner or by hand).
- * block_x * block_y threads per workgroup (multiple of 64, at most 1024);
- * rows_per_thread in {1, 2, 4}; xcd_remap != 0 maps consecutive tiles to the
- * same XCD. A zeroed struct selects the built-in default. */
+ * steps_per_launch = 1: one time step per launch; block_x * block_y threads per
+ * workgroup (multiple of 64, at most 1024), rows_per_thread in {1, 2, 4}, xcd_remap != 0
+ * maps consecutive tiles to the same XCD.
+ * steps_per_launch = 2 (FP32 storage only): two time steps per launch, the intermediate
+ * state kept in LDS by workgroups of 512 threads that own 64 x 14 node tiles (the
+ * other fields are ignored); an odd step count ends with one single step. Both modes
+ * give bitwise identical states.
+ * A zeroed struct selects the built-in default (two steps per launch for FP32 storage,
+ * one for FP16). */
 typedef struct {
     int block_x, block_y, rows_per_thread, xcd_remap;
+    int steps_per_launch;
 } clbm_launch;
 
 /* Diagnostics at the current time (Sec. 3.3 Nusselt number and a residual). */

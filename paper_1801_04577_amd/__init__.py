@@ -50,7 +50,8 @@ class clbm_params(ctypes.Structure):
 
 class clbm_launch(ctypes.Structure):
     _fields_ = [("block_x", ctypes.c_int), ("block_y", ctypes.c_int),
-                ("rows_per_thread", ctypes.c_int), ("xcd_remap", ctypes.c_int)]
+                ("rows_per_thread", ctypes.c_int), ("xcd_remap", ctypes.c_int),
+                ("steps_per_launch", ctypes.c_int)]
 
 
 class clbm_diag(ctypes.Structure):
@@ -341,15 +342,16 @@ class Solver:
     def load(self, buf, step):
         _check(lib().clbm_load(self._h, _addr(buf), int(step)), "clbm_load")
 
-    def set_launch(self, block_x=256, block_y=1, rows_per_thread=1, xcd_remap=0):
-        L = clbm_launch(int(block_x), int(block_y), int(rows_per_thread), int(xcd_remap))
+    def set_launch(self, block_x=256, block_y=1, rows_per_thread=1, xcd_remap=0, steps_per_launch=1):
+        L = clbm_launch(int(block_x), int(block_y), int(rows_per_thread), int(xcd_remap),
+                        int(steps_per_launch))
         _check(lib().clbm_set_launch(self._h, ctypes.byref(L)), "clbm_set_launch")
 
     def get_launch(self):
         L = clbm_launch()
         _check(lib().clbm_get_launch(self._h, ctypes.byref(L)), "clbm_get_launch")
         return {"block_x": L.block_x, "block_y": L.block_y, "rows_per_thread": L.rows_per_thread,
-                "xcd_remap": L.xcd_remap}
+                "xcd_remap": L.xcd_remap, "steps_per_launch": L.steps_per_launch}
 
     def set_graph(self, steps_per_graph):
         _check(lib().clbm_set_graph(self._h, int(steps_per_graph)), "clbm_set_graph")

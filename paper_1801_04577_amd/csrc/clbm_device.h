@@ -91,28 +91,35 @@ template <> struct Wide<__half> { typedef float type; };
 __device__ __forceinline__ unsigned hash_bits(double x) { return (unsigned)__double_as_longlong(x); }
 __device__ __forceinline__ unsigned hash_bits(float x) { return __float_as_uint(x); }
 
-// Store x with the unbiased rounding; r is a uniform 32-bit variate.
-template <typename S> __device__ __forceinline__ void st_sr(S* p, typename Wide<S>::type x, unsigned r);
+// x rounded into the storage type S with the unbiased rounding; r is a uniform 32-bit
+// variate.
 // FP64 -> FP32: add the top 29 bits of r to the 52-bit mantissa and truncate the 29 bits
 // FP32 does not keep; the conversion of the truncated value is then exact. The magnitude
 // rounds up with probability (discarded bits)/2^29.
-template <> __device__ __forceinline__ void st_sr<float>(float* p, double x, unsigned r)
+__device__ __forceinline__ float sr_round(double x, unsigned r)
 {
     unsigned long long bits = (unsigned long long)__double_as_longlong(x);
     bits += (unsigned long long)(r >> 3);
     bits &= ~0x1FFFFFFFull;
-    __builtin_nontemporal_store((float)__longlong_as_double((long long)bits), p);
+    return (float)__longlong_as_double((long long)bits);
 }
 // FP32 -> binary16 with gfx950's stochastic-rounding conversion: the magnitude rounds up
 // with probability equal to the discarded fraction of a binary16 ulp (subnormal spacing
 // 2^-24 included), the random bits taken from the top of r.
-template <> __device__ __forceinline__ void st_sr<__half>(__half* p, float x, unsigned r)
+__device__ __forceinline__ __half sr_round(float x, unsigned r)
 {
     typedef _Float16 half2v __attribute__((ext_vector_type(2)));
     const half2v v = __builtin_amdgcn_cvt_sr_f16_f32(half2v{0, 0}, x, r, false);
     __half_raw raw;
     raw.data = v[0];
-    __builtin_nontemporal_store(raw.x, reinterpret_cast<unsigned short*>(p));
+    return raw;
+}
+
+// Nontemporal stores of storage values.
+__device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_nt(__half* p, __half v)
+{
+    __builtin_nontemporal_store(__half_raw(v).x, reinterpret_cast<unsigned short*>(p));
 }
 
 struct NodeMacro {

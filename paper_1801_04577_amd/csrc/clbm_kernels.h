@@ -13,29 +13,65 @@
 
 namespace clbm {
 
-// The 14 stored populations of one node.
+// Where a step reads the populations of time t: the stored buffer (GlobalMem) or, in
+// the two-step kernel, the workgroup's tile in LDS (TileMem). Each gives the element
+// offset of a neighbour's row and column part and the stride P between the populations
+// of one node. In a periodic direction GlobalMem wraps the neighbour; TileMem does not,
+// since its halo already holds the wrapped nodes.
+template <typename S>
+struct GlobalMem {
+    typedef S Elem;
+    const S* __restrict__ p;
+    unsigned rowlen;
+    int nx, ny;
+    static constexpr unsigned P = kBlock;
+    __device__ __forceinline__ unsigned row(int y, int d) const
+    {
+        int yy = y + d;
+        yy = yy < 0 ? ny - 1 : (yy >= ny ? 0 : yy);
+        return (unsigned)yy * rowlen;
+    }
+    __device__ __forceinline__ unsigned col(int x, int d) const
+    {
+        int xx = x + d;
+        xx = xx < 0 ? nx - 1 : (xx >= nx ? 0 : xx);
+        return ((unsigned)xx / kBlock) * kBlockElems + ((unsigned)xx % kBlock);
+    }
+};
+
+template <typename S>
+__device__ __forceinline__ GlobalMem<S> global_mem(const S* __restrict__ src, const LatticeConst& c)
+{
+    return GlobalMem<S>{src, c.rowlen, c.nx, c.ny};
+}
+
+// The 14 populations of the node at offset own.
+template <typename S, unsigned P>
+__device__ __forceinline__ void load_pops(const S* p, unsigned own, float a[9], float b[5])
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) a[i] = ld(p + i * P + own);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) b[i] = ld(p + (9 + i) * P + own);
+}
+
+// The 14 stored populations of one node (own = node_off).
 template <typename S>
 __device__ __forceinline__ void load_own(const S* __restrict__ src, const LatticeConst& c,
                                          unsigned own, float a[9], float b[5])
 {
-    constexpr unsigned P = kBlock;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) a[i] = ld(src + i * P + own);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) b[i] = ld(src + (9 + i) * P + own);
+    load_pops<S, kBlock>(src, own, a, b);
 }
 
-// T - T0 at time t of the node at element offset off (node_off), from its stored post-collision
+// T - T0 at time t of the node at element offset off, from its post-collision
 // populations: sum g* - Q/2, with Q the node's own source under VH.
-template <typename S, bool VH>
-__device__ __forceinline__ float theta_post(const S* __restrict__ src, const LatticeConst& c,
-                                            unsigned off)
+template <bool VH, typename S, unsigned P>
+__device__ __forceinline__ float theta_at(const S* p, const LatticeConst& c, unsigned off)
 {
-    constexpr unsigned P = kBlock;
-    const S* gs = src + 9 * P;
+    const S* gs = p + 9 * P;
     if constexpr (VH) {
         float a[9], b[5];
-        load_own(src, c, off, a, b);
+        load_pops<S, P>(p, off, a, b);
         return macros_from_post<true>(c, a, b).theta;
     } else {
         const float s = ld(gs + off) + ld(gs + P + off) + ld(gs + 2 * P + off) + ld(gs + 3 * P + off)
@@ -44,29 +80,32 @@ __device__ __forceinline__ float theta_post(const S* __restrict__ src, const Lat
     }
 }
 
+template <typename S, bool VH>
+__device__ __forceinline__ float theta_post(const S* __restrict__ src, const LatticeConst& c,
+                                            unsigned off)
+{
+    return theta_at<VH, S, kBlock>(src, c, off);
+}
+
 // Gather the pre-collision deviations of node (x, y) at time t+1 from the
-// post-collision buffer at time t, with all wall substitutions applied.
+// post-collision populations at time t, with all wall substitutions applied.
 // VH: the heat source includes the viscous dissipation (wall temperatures need the
 // source of the nodes they are extrapolated from).
-template <typename S, bool VH = false>
-__device__ __forceinline__ void gather_node(const S* __restrict__ src, const LatticeConst& c, int x,
-                                            int y, float a[9], float b[5])
+template <bool VH, typename Mem>
+__device__ __forceinline__ void gather_mem(const Mem& mem, const LatticeConst& c, int x, int y,
+                                           float a[9], float b[5])
 {
-    const int nx = c.nx, ny = c.ny;
-    constexpr unsigned P = kBlock;
-    // Source coordinates of the links; a link whose source lies outside a wall is
-    // flagged and its source clamped to the node itself (the address is never used).
-    int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
-    bool oxm = false, oxp = false, oym = false, oyp = false;
-    if (xm < 0) { if (c.periodic_x) xm = nx - 1; else { oxm = true; xm = x; } }
-    if (xp >= nx) { if (c.periodic_x) xp = 0; else { oxp = true; xp = x; } }
-    if (ym < 0) { if (c.periodic_y) ym = ny - 1; else { oym = true; ym = y; } }
-    if (yp >= ny) { if (c.periodic_y) yp = 0; else { oyp = true; yp = y; } }
-    // Offsets of the three source rows and the three source columns (node_off split).
-    const unsigned rC = (unsigned)y * c.rowlen, rM = (unsigned)ym * c.rowlen, rP = (unsigned)yp * c.rowlen;
-    auto col = [](int xx) { return ((unsigned)xx / kBlock) * kBlockElems + ((unsigned)xx % kBlock); };
-    const unsigned cM = col(xm), cC = col(x), cP = col(xp);
+    constexpr unsigned P = Mem::P;
+    // A link whose source lies outside a wall is flagged, and its source is the node
+    // itself (the address is never used).
+    const bool oxm = !c.periodic_x && x == 0, oxp = !c.periodic_x && x == c.nx - 1;
+    const bool oym = !c.periodic_y && y == 0, oyp = !c.periodic_y && y == c.ny - 1;
+    // Offsets of the three source rows and the three source columns.
+    const unsigned rC = mem.row(y, 0), cC = mem.col(x, 0);
+    const unsigned rM = oym ? rC : mem.row(y, -1), rP = oyp ? rC : mem.row(y, 1);
+    const unsigned cM = oxm ? cC : mem.col(x, -1), cP = oxp ? cC : mem.col(x, 1);
     const unsigned own = rC + cC;
+    const auto* src = mem.p;
 
     // Eq. (11) pull form f_i(x, t+1) = f_i*(x - e_i, t); a wall link takes the
     // opposite population of the node itself (half-way bounce-back).
@@ -80,7 +119,7 @@ __device__ __forceinline__ void gather_node(const S* __restrict__ src, const Lat
     a[7] = ld(src + ((oxp | oyp) ? 5 * P + own : 7 * P + rP + cP));
     a[8] = ld(src + ((oxm | oyp) ? 6 * P + own : 8 * P + rP + cM));
     // Eq. (21); a wall link loads the opposite population of the node, completed below.
-    const S* gs = src + 9 * P;
+    const auto* gs = src + 9 * P;
     b[0] = ld(gs + own);
     b[1] = ld(gs + (oxm ? 3 * P + own : 1 * P + rC + cM));
     b[2] = ld(gs + (oym ? 4 * P + own : 2 * P + rM + cC));
@@ -90,23 +129,23 @@ __device__ __forceinline__ void gather_node(const S* __restrict__ src, const Lat
     if (oxm | oxp | oym | oyp) {
         // Eq. (26): g_i(x_f, t+1) = -g*_opp(i)(x_f, t) + c_T^2 T_w, with T_w from Eq. (28)
         // using T at this node (T1) and one node further from the wall (T2) at time t.
-        // Stored post-collision data give T = sum g* - Q/2 (the collision adds Q).
-        auto theta_at = [&](unsigned off) { return theta_post<S, VH>(src, c, off); };
-        const float th1 = theta_at(own);
+        // Post-collision data give T = sum g* - Q/2 (the collision adds Q).
+        auto theta = [&](unsigned off) { return theta_at<VH, typename Mem::Elem, P>(src, c, off); };
+        const float th1 = theta(own);
         if (oxm) {
-            const float tw = c.a1[0] * th1 + c.a2[0] * theta_at(node_off(c, x + 1, y)) + c.a3[0];
+            const float tw = c.a1[0] * th1 + c.a2[0] * theta(rC + mem.col(x, 1)) + c.a3[0];
             b[1] = -b[1] + CT2 * tw;
         }
         if (oxp) {
-            const float tw = c.a1[1] * th1 + c.a2[1] * theta_at(node_off(c, x - 1, y)) + c.a3[1];
+            const float tw = c.a1[1] * th1 + c.a2[1] * theta(rC + mem.col(x, -1)) + c.a3[1];
             b[3] = -b[3] + CT2 * tw;
         }
         if (oym) {
-            const float tw = c.a1[2] * th1 + c.a2[2] * theta_at(own + c.rowlen) + c.a3[2];
+            const float tw = c.a1[2] * th1 + c.a2[2] * theta(mem.row(y, 1) + cC) + c.a3[2];
             b[2] = -b[2] + CT2 * tw;
         }
         if (oyp) {
-            const float tw = c.a1[3] * th1 + c.a2[3] * theta_at(own - c.rowlen) + c.a3[3];
+            const float tw = c.a1[3] * th1 + c.a2[3] * theta(mem.row(y, -1) + cC) + c.a3[3];
             b[4] = -b[4] + CT2 * tw;
         }
         if (c.moving) {
@@ -128,16 +167,22 @@ __device__ __forceinline__ void gather_node(const S* __restrict__ src, const Lat
     }
 }
 
-// Store the post-collision state of one node: the deviations, computed wider than the
-// storage, with the unbiased rounding of st_sr. One hash per node mixes the bits of all
-// 14 results; the k-th store takes h + k * 0x9E3779B9 (a Weyl sequence), each uniform
-// on its own.
-template <typename S>
-__device__ __forceinline__ void store_node(S* __restrict__ dst, const LatticeConst& c, unsigned own,
-                                           const typename Wide<S>::type fa[9],
-                                           const typename Wide<S>::type tb[5])
+// Gather from the stored buffer.
+template <typename S, bool VH = false>
+__device__ __forceinline__ void gather_node(const S* __restrict__ src, const LatticeConst& c, int x,
+                                            int y, float a[9], float b[5])
 {
-    constexpr unsigned P = kBlock;
+    gather_mem<VH>(global_mem(src, c), c, x, y, a, b);
+}
+
+// Round the post-collision state of one node into the storage type: the deviations,
+// computed wider than the storage, go through the unbiased rounding of sr_round. One
+// hash per node mixes the bits of all 14 results; the k-th value takes
+// h + k * 0x9E3779B9 (a Weyl sequence), each uniform on its own.
+template <typename S>
+__device__ __forceinline__ void round_node(const typename Wide<S>::type fa[9],
+                                           const typename Wide<S>::type tb[5], S out[14])
+{
     unsigned acc = 0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) acc = ((acc << 5) | (acc >> 27)) ^ hash_bits(fa[i]);
@@ -145,11 +190,22 @@ __device__ __forceinline__ void store_node(S* __restrict__ dst, const LatticeCon
     for (int i = 0; i < 5; ++i) acc = ((acc << 5) | (acc >> 27)) ^ hash_bits(tb[i]);
     const unsigned h = mix32(acc);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) st_sr(dst + i * P + own, fa[i], h + (unsigned)i * 0x9E3779B9u);
+    for (int i = 0; i < 9; ++i) out[i] = sr_round(fa[i], h + (unsigned)i * 0x9E3779B9u);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) st_sr(dst + (9 + i) * P + own, tb[i], h + (unsigned)(9 + i) * 0x9E3779B9u);
+    for (int i = 0; i < 5; ++i) out[9 + i] = sr_round(tb[i], h + (unsigned)(9 + i) * 0x9E3779B9u);
 }
 
+// Store the post-collision state of one node (own = node_off), nontemporal.
+template <typename S>
+__device__ __forceinline__ void store_node(S* __restrict__ dst, const LatticeConst& c, unsigned own,
+                                           const typename Wide<S>::type fa[9],
+                                           const typename Wide<S>::type tb[5])
+{
+    S v[14];
+    round_node<S>(fa, tb, v);
+#pragma unroll
+    for (int i = 0; i < 14; ++i) st_nt(dst + i * kBlock + own, v[i]);
+}
 
 // Tile -> workgroup map. With xcd_remap the grid is padded to a multiple of 8 and
 // workgroup b (dispatched to XCD b % 8) takes tile (b % 8) * (grid/8) + b/8, so
@@ -187,4 +243,109 @@ __global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __r
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two time steps per launch. A workgroup owns a tile of kBlock columns by TY rows.
+// Phase 1 advances the tile and a ring of one node around it from t to t+1 (pulling
+// from the stored buffer) and keeps the results in LDS, rounded exactly as the stored
+// state would be; phase 2 advances the tile from t+1 to t+2, pulling from LDS, and
+// stores it. Both phases run the per-node code of k_step, so one launch equals two
+// launches of k_step bit for bit, while each stored population is read about
+// (1 + 2/kBlock)(1 + 2/TY) times and written once per two steps.
+// ---------------------------------------------------------------------------
+
+template <int TY>
+struct Tile2 {
+    static constexpr int XE = kBlock + 2, YE = TY + 2;  // with the halo ring
+    static constexpr unsigned P = XE * YE;              // LDS population stride
+};
+
+// LDS tile [14][YE][XE] of the two-step kernel; element (0, 0) is global node (x0, y0).
+template <typename S, int TY>
+struct TileMem {
+    typedef S Elem;
+    const S* p;
+    int x0, y0;
+    static constexpr unsigned P = Tile2<TY>::P;
+    __device__ __forceinline__ unsigned row(int y, int d) const { return (unsigned)(y + d - y0) * Tile2<TY>::XE; }
+    __device__ __forceinline__ unsigned col(int x, int d) const { return (unsigned)(x + d - x0); }
+};
+
+__device__ __forceinline__ int wrap_index(int g, int n)
+{
+    g = g < 0 ? g + n : g;
+    return g >= n ? g % n : g;
+}
+
+// Phase 1 for thread tid of the workgroup whose tile starts at (X0, Y0): node
+// (X0 - 1 + lx, Y0 - 1 + ly) of the tile with its ring, advanced from the stored buffer
+// into LDS. In a periodic direction a ring node outside the lattice is the wrapped
+// node; in a walled one it does not exist and its LDS entry is never read.
+template <typename S, bool VH, int TY, int NT>
+__device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const LatticeConst& c, S* tile,
+                                             int X0, int Y0, int tid)
+{
+    typedef typename Wide<S>::type W;
+    typedef Tile2<TY> T;
+    const int lane = tid % 64, wave = tid / 64;
+    constexpr int nwaves = NT / 64;
+    auto advance = [&](int lx, int ly) {
+        int gx = X0 - 1 + lx, gy = Y0 - 1 + ly;
+        if (gx < 0 || gx >= c.nx) {
+            if (!c.periodic_x) return;
+            gx = wrap_index(gx, c.nx);
+        }
+        if (gy < 0 || gy >= c.ny) {
+            if (!c.periodic_y) return;
+            gy = wrap_index(gy, c.ny);
+        }
+        float a[9], b[5];
+        W fa[9], tb[5];
+        NodeMacro m;
+        gather_node<S, VH>(src, c, gx, gy, a, b);
+        collide<W, VH>(c, a, b, fa, tb, m);
+        S v[14];
+        round_node<S>(fa, tb, v);
+        const unsigned o = (unsigned)ly * T::XE + lx;
+#pragma unroll
+        for (int i = 0; i < 14; ++i) tile[i * T::P + o] = v[i];
+    };
+    // one wave per row for the kBlock interior columns, then the two ring columns
+    for (int ly = wave; ly < T::YE; ly += nwaves) advance(lane + 1, ly);
+    for (int k = tid; k < 2 * T::YE; k += NT) advance(k < T::YE ? 0 : T::XE - 1, k % T::YE);
+}
+
+// Phase 2 for thread tid: the tile's own nodes advanced from LDS and stored.
+template <typename S, bool VH, int TY, int NT>
+__device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeConst& c, const S* tile,
+                                             int X0, int Y0, int tid)
+{
+    typedef typename Wide<S>::type W;
+    const int lane = tid % 64, wave = tid / 64;
+    constexpr int nwaves = NT / 64;
+    const TileMem<S, TY> mem{tile, X0 - 1, Y0 - 1};
+    const int gx = X0 + lane;
+    if (gx >= c.nx) return;
+    for (int ly = wave; ly < TY; ly += nwaves) {
+        const int gy = Y0 + ly;
+        if (gy >= c.ny) break;
+        float a[9], b[5];
+        W fa[9], tb[5];
+        NodeMacro m;
+        gather_mem<VH>(mem, c, gx, gy, a, b);
+        collide<W, VH>(c, a, b, fa, tb, m);
+        store_node(dst, c, node_off(c, gx, gy), fa, tb);
+    }
+}
+
+template <typename S, bool VH, int TY, int NT>
+__global__ void __launch_bounds__(NT) k_step2(const S* __restrict__ src, S* __restrict__ dst,
+                                              const LatticeConst c, int tiles_x)
+{
+    __shared__ S tile[14 * Tile2<TY>::P];
+    const int X0 = (int)(blockIdx.x % (unsigned)tiles_x) * (int)kBlock;
+    const int Y0 = (int)(blockIdx.x / (unsigned)tiles_x) * TY;
+    step2_phase1<S, VH, TY, NT>(src, c, tile, X0, Y0, (int)threadIdx.x);
+    __syncthreads();
+    step2_phase2<S, VH, TY, NT>(dst, c, tile, X0, Y0, (int)threadIdx.x);
+}
 }  // namespace clbm

@@ -194,21 +194,46 @@ static StepLaunch plan_step(const LatticeConst& c, int precision, const clbm_lau
     return s;
 }
 
-static bool launch_ok(const clbm_launch& L)
+static bool launch_ok(const clbm_launch& L, int precision)
 {
+    if (L.steps_per_launch == 2) return precision == CLBM_FP32;
+    if (L.steps_per_launch != 1) return false;
     const int threads = L.block_x * L.block_y;
     if (L.block_x < 1 || L.block_y < 1 || threads % 64 != 0 || threads > 1024) return false;
     return L.rows_per_thread == 1 || L.rows_per_thread == 2 || L.rows_per_thread == 4;
 }
 
-static clbm_launch default_launch()
+static clbm_launch default_launch(int precision)
 {
     clbm_launch L;
     L.block_x = 256;
     L.block_y = 1;
     L.rows_per_thread = 1;
     L.xcd_remap = 0;
+    L.steps_per_launch = precision == CLBM_FP32 ? 2 : 1;
     return L;
+}
+
+// Two steps per launch (FP32 storage): tiles of kBlock x kTwoStepRows nodes.
+constexpr int kTwoStepRows = 14;
+constexpr int kTwoStepThreads = 512;
+
+struct Step2Launch {
+    const void* fn;
+    dim3 grid, block;
+    int tiles_x;
+};
+
+static Step2Launch plan_step2(const LatticeConst& c)
+{
+    Step2Launch s;
+    s.fn = c.viscous ? reinterpret_cast<const void*>(&k_step2<float, true, kTwoStepRows, kTwoStepThreads>)
+                     : reinterpret_cast<const void*>(&k_step2<float, false, kTwoStepRows, kTwoStepThreads>);
+    s.tiles_x = (c.nx + (int)kBlock - 1) / (int)kBlock;
+    const int tiles_y = (c.ny + kTwoStepRows - 1) / kTwoStepRows;
+    s.grid = dim3((unsigned)(s.tiles_x * tiles_y), 1, 1);
+    s.block = dim3(kTwoStepThreads, 1, 1);
+    return s;
 }
 
 }  // namespace clbm
@@ -271,53 +296,93 @@ void drop_graphs(clbm_handle* h)
     }
 }
 
+// One kernel launch advancing the state by one or two steps from buffer `from`.
+struct LaunchArgs {
+    void* src;
+    void* dst;
+    LatticeConst c;
+    int a0, a1, a2;
+};
+
+// The launches of n steps: two-step launches while two or more steps remain (when
+// enabled), then single steps. Calls emit(fn, grid, block, args) for each.
+template <typename Emit>
+clbm_status plan_steps(clbm_handle* h, int n, int from, Emit emit)
+{
+    const bool two = h->launch.steps_per_launch == 2;
+    const StepLaunch s1 = plan_step(h->c, h->p.precision, h->launch);
+    const Step2Launch s2 = plan_step2(h->c);
+    int cur = from;
+    while (n > 0) {
+        LaunchArgs a;
+        a.src = h->buf[cur];
+        a.dst = h->buf[cur ^ 1];
+        a.c = h->c;
+        if (two && n >= 2) {
+            a.a0 = s2.tiles_x;
+            void* args[] = {&a.src, &a.dst, &a.c, &a.a0};
+            clbm_status st = emit(s2.fn, s2.grid, s2.block, args);
+            if (st != CLBM_OK) return st;
+            n -= 2;
+        } else {
+            a.a0 = s1.tiles_x;
+            a.a1 = s1.tiles_total;
+            a.a2 = s1.remap;
+            void* args[] = {&a.src, &a.dst, &a.c, &a.a0, &a.a1, &a.a2};
+            clbm_status st = emit(s1.fn, s1.grid, s1.block, args);
+            if (st != CLBM_OK) return st;
+            n -= 1;
+        }
+        cur ^= 1;
+    }
+    return CLBM_OK;
+}
+
+// Number of launches (buffer flips) of n steps.
+int launches_of(const clbm_handle* h, int n)
+{
+    return h->launch.steps_per_launch == 2 ? n / 2 + n % 2 : n;
+}
+
 clbm_status launch_steps_direct(clbm_handle* h, int n)
 {
-    const StepLaunch s = plan_step(h->c, h->p.precision, h->launch);
-    for (int k = 0; k < n; ++k) {
-        void* src = h->buf[h->cur];
-        void* dst = h->buf[h->cur ^ 1];
-        LatticeConst c = h->c;
-        int tx = s.tiles_x, tt = s.tiles_total, rm = s.remap;
-        void* args[] = {&src, &dst, &c, &tx, &tt, &rm};
-        CLBM_HIP(hipLaunchKernel(s.fn, s.grid, s.block, args, 0, h->stream));
-        h->cur ^= 1;
-        h->step++;
-    }
+    clbm_status st = plan_steps(h, n, h->cur, [&](const void* fn, dim3 g, dim3 b, void** args) {
+        CLBM_HIP(hipLaunchKernel(fn, g, b, args, 0, h->stream));
+        return CLBM_OK;
+    });
+    if (st != CLBM_OK) return st;
+    h->cur ^= launches_of(h, n) & 1;
+    h->step += n;
     return CLBM_OK;
 }
 
 clbm_status build_graph(clbm_handle* h, int start)
 {
-    const StepLaunch s = plan_step(h->c, h->p.precision, h->launch);
     hipGraph_t g = nullptr;
     CLBM_HIP(hipGraphCreate(&g, 0));
     hipGraphNode_t prev = nullptr;
-    int cur = start;
-    // Argument storage must outlive hipGraphAddKernelNode only (it copies the values).
-    for (int k = 0; k < h->graph_steps; ++k) {
-        void* src = h->buf[cur];
-        void* dst = h->buf[cur ^ 1];
-        LatticeConst c = h->c;
-        int tx = s.tiles_x, tt = s.tiles_total, rm = s.remap;
-        void* args[] = {&src, &dst, &c, &tx, &tt, &rm};
+    // hipGraphAddKernelNode copies the argument values.
+    clbm_status st = plan_steps(h, h->graph_steps, start, [&](const void* fn, dim3 gd, dim3 bd, void** args) {
         hipKernelNodeParams kp;
         std::memset(&kp, 0, sizeof kp);
-        kp.func = const_cast<void*>(s.fn);
-        kp.gridDim = s.grid;
-        kp.blockDim = s.block;
+        kp.func = const_cast<void*>(fn);
+        kp.gridDim = gd;
+        kp.blockDim = bd;
         kp.sharedMemBytes = 0;
         kp.kernelParams = args;
         kp.extra = nullptr;
         hipGraphNode_t node;
         hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
         if (e != hipSuccess) {
-            (void)hipGraphDestroy(g);
             set_last_hip_error(e, "hipGraphAddKernelNode", __FILE__, __LINE__);
             return CLBM_ERR_HIP;
         }
         prev = node;
-        cur ^= 1;
+        return CLBM_OK;
+    });
+    if (st != CLBM_OK) {
+        (void)hipGraphDestroy(g);
+        return st;
     }
     hipGraphExec_t ex = nullptr;
     hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -403,7 +468,7 @@ clbm_status clbm_create(const clbm_params* p, void* d_workspace, size_t bytes, v
     h->snap = (float*)(ws + o_snap);
     h->partial = (double*)(ws + o_part);
     h->result = (double*)(ws + o_res);
-    h->launch = default_launch();
+    h->launch = default_launch(p->precision);
     h->graph_steps = 0;
     h->snap_step = -1;
     st = clbm_init_from_fields(h, nullptr, nullptr, nullptr, nullptr);
@@ -452,7 +517,7 @@ clbm_status clbm_step(clbm_handle* h, int nsteps)
                 if (st != CLBM_OK) return st;
             }
             CLBM_HIP(hipGraphLaunch(h->gexec[h->cur], h->stream));
-            // graph_steps is even: the state returns to the same buffer.
+            h->cur ^= launches_of(h, h->graph_steps) & 1;
             h->step += h->graph_steps;
             left -= h->graph_steps;
         }
@@ -580,8 +645,23 @@ clbm_status clbm_set_launch(clbm_handle* h, const clbm_launch* launch)
 {
     if (!h || !launch) return CLBM_ERR_INVALID_ARG;
     clbm_launch L = *launch;
-    if (L.block_x == 0 && L.block_y == 0 && L.rows_per_thread == 0) L = default_launch();
-    if (!launch_ok(L)) return CLBM_ERR_INVALID_ARG;
+    if (L.block_x == 0 && L.block_y == 0 && L.rows_per_thread == 0 && L.xcd_remap == 0 &&
+        L.steps_per_launch == 0)
+        L = default_launch(h->p.precision);
+    if (L.steps_per_launch == 2) {
+        // the single step that ends an odd step count uses the default shape unless a
+        // valid one is given
+        clbm_launch one = L;
+        one.steps_per_launch = 1;
+        if (!launch_ok(one, h->p.precision)) {
+            const clbm_launch d = default_launch(CLBM_FP16_SHIFTED);
+            L.block_x = d.block_x;
+            L.block_y = d.block_y;
+            L.rows_per_thread = d.rows_per_thread;
+            L.xcd_remap = d.xcd_remap;
+        }
+    }
+    if (!launch_ok(L, h->p.precision)) return CLBM_ERR_INVALID_ARG;
     h->launch = L;
     drop_graphs(h);
     return CLBM_OK;

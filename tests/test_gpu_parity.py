@@ -181,6 +181,38 @@ def test_launch_shapes_are_bitwise_identical(launch):
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("seed", [0, 3, 5, 9, 11])
+@pytest.mark.parametrize("steps", [1, 2, 37])
+def test_two_step_launches_equal_single_steps(seed, steps):
+    """Two time steps per launch (intermediate state in LDS) against one step per launch:
+    bitwise identical states, also for an odd count (the last step runs alone) and through
+    replayed graphs of 6 steps (three two-step launches)."""
+    import torch
+    prob, fields = random_case(seed)
+    a = run_gpu(prob, steps, fields, launch=dict(block_x=256, steps_per_launch=1))
+    b = run_gpu(prob, steps, fields, launch=dict(steps_per_launch=2))
+    c = run_gpu(prob, steps + 12, fields, launch=dict(steps_per_launch=2), graph=6)
+    d = run_gpu(prob, steps + 12, fields, launch=dict(block_x=256, steps_per_launch=1))
+    for x, y in zip(a.populations(), b.populations()):
+        assert torch.equal(x, y)
+    for x, y in zip(c.populations(), d.populations()):
+        assert torch.equal(x, y)
+
+
+def test_two_step_launch_viscous_and_fp16_rules():
+    import torch
+    import paper_1801_04577_amd as clbm
+    prob = dict(W.viscous_channel(32, nx=150), Q=1e-6)
+    a = run_gpu(prob, 41, None, launch=dict(block_x=256, steps_per_launch=1))
+    b = run_gpu(prob, 41, None, launch=dict(steps_per_launch=2))
+    for x, y in zip(a.populations(), b.populations()):
+        assert torch.equal(x, y)
+    s = clbm.Solver(W.channel(), clbm.CLBM_FP16_SHIFTED)
+    assert s.get_launch()["steps_per_launch"] == 1
+    with pytest.raises(clbm.ClbmError):
+        s.set_launch(steps_per_launch=2)
+
+
 def test_checkpoint_resume_bitwise():
     import torch
     prob, fields = random_case(11)
