@@ -100,11 +100,11 @@ typedef struct {
  * workgroup (multiple of 64, at most 1024), rows_per_thread in {1, 2, 4}, xcd_remap != 0
  * maps consecutive tiles to the same XCD.
  * steps_per_launch = 2 (FP32 storage only): two time steps per launch, the intermediate
- * state kept in LDS by workgroups of 512 threads that own 64 x 14 node tiles (the
- * other fields are ignored); an odd step count ends with one single step. Both modes
- * give bitwise identical states.
- * A zeroed struct selects the built-in default (two steps per launch for FP32 storage,
- * one for FP16). */
+ * state kept in LDS by workgroups of 512 threads that own 64 x 14 node tiles; xcd_remap
+ * applies to these tiles too, the other fields shape only the single step that ends an
+ * odd step count. Both modes give bitwise identical states.
+ * A zeroed struct selects the built-in default (two steps per launch with xcd_remap for
+ * FP32 storage, one step per launch for FP16). */
 typedef struct {
     int block_x, block_y, rows_per_thread, xcd_remap;
     int steps_per_launch;

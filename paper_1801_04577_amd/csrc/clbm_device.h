@@ -39,11 +39,11 @@ struct LatticeConst {
     unsigned rowlen;           // elements per stored row: ceil(nx / kBlock) * kBlockElems
     int periodic_x, periodic_y;
     int moving;                // any wall with u_wall != 0
-    float one_m_sp, sm;        // 1 - s_plus, s_minus  (Eq. 8 block on k20, k02)
-    float one_m_snu;           // 1 - s_nu on k11
-    float one_m_s3, half_s3c;  // 1 - s_3 and (1 - s_3/2)/3 (force term on k21, k12)
-    float one_m_s4;            // 1 - s_4 on k22
-    float one_m_l1, one_m_l2;  // thermal 1 - lambda_1, 1 - lambda_2
+    float sp, sm;              // s_plus, s_minus (Eq. 8 block on k20, k02)
+    float snu;                 // s_nu on k11
+    float s3, half_s3c;        // s_3 and (1 - s_3/2)/3 (force term on k21, k12)
+    float s4;                  // s_4 on k22
+    float l1, l2;              // thermal lambda_1, lambda_2
     float src2;                // (1 - lambda_2/2) c_T^2 Q (source on thermal k20, k02)
     float g_beta, Fx, Fy, Q, T0;
     int viscous;               // add the viscous dissipation to Q (Sec. 3.2)
@@ -129,47 +129,44 @@ struct NodeMacro {
 };
 
 // Cascaded collision of the temperature populations (Eq. 13-20 with the heat source
-// of Eq. 23-24), evaluated in FP64 registers from the FP32 inputs. The arithmetic is
-// done wider than the storage so that the only rounding left in a time step is the
-// unbiased one into storage: a heat source adds the same non-representable amount
-// every step, and round-to-nearest of that increment onto the storage grid would
-// otherwise bias the temperature by a fixed fraction of an ulp per step.
+// of Eq. 23-24), in the wide type R. The collision changes the central moments by
+// Delta k00 = Q (the zeroth moment relaxes to T + Q/2 whatever lambda_0),
+// Delta k10 = -lambda_1 k10, Delta k01 = -lambda_1 k01 and
+// Delta k20 = -lambda_2 (k20 - c_T^2 T) + (1 - lambda_2/2) c_T^2 Q (k02 alike); the
+// change is shifted back to raw moments (inverse of Eq. 17) and to populations
+// (inverse of Eq. 16) and added to the incoming populations, tb = b + Delta g.
 template <typename R>
 __device__ __forceinline__ void collide_thermal(const LatticeConst& c, const float b[5], R ux,
                                                 R uy, R Q, R src2, R tb[5])
 {
     const R T0 = c.T0;
     const R b0 = b[0], b1 = b[1], b2 = b[2], b3 = b[3], b4 = b[4];
-    const R ux2 = ux * ux, uy2 = uy * uy;
     // Raw moments of b (Eq. 16); the rest weights carry [T0, 0, 0, T0 c_T^2, T0 c_T^2].
     const R sb = (b0 + b1) + (b2 + b3) + b4;
     const R theta = sb + R(0.5) * Q;               // Eq. (25), minus T0
     const R t10 = b1 - b3, t01 = b2 - b4, t20 = b1 + b3, t02 = b2 + b4;
-    const R K00 = T0 + sb;                      // full raw k00 = T - Q/2
-    // Central moments (Eq. 17) minus equilibria (Eq. 19).
+    const R K00 = T0 + sb;                          // full raw k00 = T - Q/2
+    // Central moments (Eq. 17) minus their equilibria (Eq. 19).
     const R e10 = t10 - ux * K00;
     const R e01 = t01 - uy * K00;
-    const R m20 = t20 - R(0.4) * theta - R(2.0) * ux * t10 + ux2 * K00;
-    const R m02 = t02 - R(0.4) * theta - R(2.0) * uy * t01 + uy2 * K00;
-    // Eq. (23): k00 relaxes to T + Q/2 for any lambda_0; lambda_1 on k10, k01;
-    // lambda_2 on k20, k02 with the source (1 - lambda_2/2) c_T^2 Q.
-    const R e10s = (R)c.one_m_l1 * e10;
-    const R e01s = (R)c.one_m_l1 * e01;
-    const R m20s = (R)c.one_m_l2 * m20 + src2;
-    const R m02s = (R)c.one_m_l2 * m02 + src2;
-    // Back to raw moments (shift by -u): k00* = T + Q/2 = T0 + Th.
-    const R Th = theta + R(0.5) * Q;
-    const R K00s = T0 + Th;
-    const R q10 = e10s + ux * K00s;
-    const R q01 = e01s + uy * K00s;
-    const R q20 = R(0.4) * theta + m20s + R(2.0) * ux * e10s + ux2 * K00s;   // k20* - T0 c_T^2
-    const R q02 = R(0.4) * theta + m02s + R(2.0) * uy * e01s + uy2 * K00s;
-    // Inverse of Eq. (16).
-    tb[0] = Th - q20 - q02;
-    tb[1] = R(0.5) * (q20 + q10);
-    tb[3] = R(0.5) * (q20 - q10);
-    tb[2] = R(0.5) * (q02 + q01);
-    tb[4] = R(0.5) * (q02 - q01);
+    const R m20 = t20 - R(0.4) * theta - R(2.0) * ux * t10 + ux * ux * K00;
+    const R m02 = t02 - R(0.4) * theta - R(2.0) * uy * t01 + uy * uy * K00;
+    // Eq. (23): changes of the central moments.
+    const R d10 = -(R)c.l1 * e10;
+    const R d01 = -(R)c.l1 * e01;
+    const R d20 = src2 - (R)c.l2 * m20;
+    const R d02 = src2 - (R)c.l2 * m02;
+    // Shift by -u (inverse of Eq. 17) with Delta k00 = Q.
+    const R r10 = d10 + ux * Q;
+    const R r01 = d01 + uy * Q;
+    const R r20 = d20 + ux * (R(2.0) * d10 + ux * Q);
+    const R r02 = d02 + uy * (R(2.0) * d01 + uy * Q);
+    // Inverse of Eq. (16), added to the incoming populations.
+    tb[0] = b0 + (Q - r20 - r02);
+    tb[1] = b1 + R(0.5) * (r20 + r10);
+    tb[3] = b3 + R(0.5) * (r20 - r10);
+    tb[2] = b2 + R(0.5) * (r02 + r01);
+    tb[4] = b4 + R(0.5) * (r02 - r01);
 }
 
 // Viscous dissipation nu [(d_x u_y + d_y u_x)^2 + (d_x u_x - d_y u_y)^2] (Sec. 3.2 uses
@@ -195,6 +192,11 @@ __device__ __forceinline__ R dissipation(float coef, R c11, R c2d, R rho)
 // heat source adds the same non-representable amount every step, and round-to-nearest of
 // those increments in storage-precision arithmetic would otherwise bias the velocity and
 // the temperature by a fixed fraction of an ulp per step.
+// The collision is evaluated as a change: Eq. (7) changes the central moments by
+// Delta = -S (k - k_eq) + (I - S/2) C, which vanishes on the conserved k00 and is the
+// force on k10, k01; the change is shifted back to raw moments with N(-u) (the inverse
+// of Eq. 6b) and to populations with the inverse of Eq. (6a), and added to the incoming
+// populations: f* = f + M^-1 N(-u) Delta.
 // VH: the heat source is Q plus the local viscous dissipation (needs g_beta = 0, so
 // that the force does not depend on the temperature the source produces).
 template <typename R, bool VH = false>
@@ -235,9 +237,7 @@ __device__ __forceinline__ void collide(const LatticeConst& c, const float a_in[
     const R uy = (jy + R(0.5) * Fy) * inv;
     const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
 
-    // Central moments (Eq. 6b), minus their equilibria (Eq. 9).
-    const R c10 = jx - ux * rho;
-    const R c01 = jy - uy * rho;
+    // Central moments (Eq. 6b) of the relaxed orders, minus their equilibria (Eq. 9).
     const R K20 = third + k20;                  // full raw k20
     const R K02 = third + k02;
     const R n20 = (k20 - d * third) - R(2) * ux * jx + ux2 * rho;
@@ -249,40 +249,37 @@ __device__ __forceinline__ void collide(const LatticeConst& c, const float a_in[
                   + uy2 * K20 + ux2 * K02 - R(2) * ux * uy2 * jx - R(2) * ux2 * uy * jy
                   + ux2 * uy2 * rho;
 
-    // Eq. (7): relaxation with the force term (I - S/2) C; rows 0-2 are not relaxed.
-    const R c10s = c10 + Fx;
-    const R c01s = c01 + Fy;
-    const R n20s = c.one_m_sp * n20 - c.sm * n02;
-    const R n02s = c.one_m_sp * n02 - c.sm * n20;
-    const R c11s = c.one_m_snu * c11;
-    const R c21s = c.one_m_s3 * c21 + c.half_s3c * Fy;
-    const R c12s = c.one_m_s3 * c12 + c.half_s3c * Fx;
-    const R n22s = c.one_m_s4 * n22;
+    // Eq. (7): changes of the central moments; on k10, k01 the change is the force.
+    const R D20 = -((R)c.sp * n20 + (R)c.sm * n02);
+    const R D02 = -((R)c.sp * n02 + (R)c.sm * n20);
+    const R D11 = -(R)c.snu * c11;
+    const R D21 = (R)c.half_s3c * Fy - (R)c.s3 * c21;
+    const R D12 = (R)c.half_s3c * Fx - (R)c.s3 * c12;
+    const R D22 = -(R)c.s4 * n22;
 
-    // Back to raw moments (shift by -u), minus the rest-weight moments.
-    const R K20s = third + d * third + n20s;    // full central k20*
-    const R K02s = third + d * third + n02s;
-    const R r10 = c10s + ux * rho;
-    const R r01 = c01s + uy * rho;
-    const R r20 = d * third + n20s + R(2) * ux * c10s + ux2 * rho;
-    const R r02 = d * third + n02s + R(2) * uy * c01s + uy2 * rho;
-    const R r11 = c11s + uy * c10s + ux * c01s + uxy * rho;
-    const R r21 = c21s + R(2) * ux * c11s + uy * K20s + R(2) * uxy * c10s + ux2 * c01s + ux2 * uy * rho;
-    const R r12 = c12s + R(2) * uy * c11s + ux * K02s + R(2) * uxy * c01s + uy2 * c10s + uy2 * ux * rho;
-    const R r22 = d * ninth + n22s + R(2) * ux * c12s + R(2) * uy * c21s + R(4) * uxy * c11s
-                  + uy2 * K20s + ux2 * K02s + R(2) * ux * uy2 * c10s + R(2) * ux2 * uy * c01s
-                  + ux2 * uy2 * rho;
+    // Shift by -u (inverse of Eq. 6b); Delta k00 = 0.
+    const R R20 = D20 + R(2) * ux * Fx;
+    const R R02 = D02 + R(2) * uy * Fy;
+    const R R11 = D11 + uy * Fx + ux * Fy;
+    const R R21 = D21 + R(2) * ux * D11 + uy * D20 + R(2) * uxy * Fx + ux2 * Fy;
+    const R R12 = D12 + R(2) * uy * D11 + ux * D02 + R(2) * uxy * Fy + uy2 * Fx;
+    const R R22 = D22 + R(2) * ux * D12 + R(2) * uy * D21 + R(4) * uxy * D11 + uy2 * D20 + ux2 * D02
+                  + R(2) * uxy * (uy * Fx + ux * Fy);
 
-    // Inverse of Eq. (6a).
-    fa[0] = d - r20 - r02 + r22;
-    fa[1] = R(0.5) * (r10 + r20 - r12 - r22);
-    fa[3] = R(0.5) * (-r10 + r20 + r12 - r22);
-    fa[2] = R(0.5) * (r01 + r02 - r21 - r22);
-    fa[4] = R(0.5) * (-r01 + r02 + r21 - r22);
-    fa[5] = R(0.25) * (r11 + r21 + r12 + r22);
-    fa[6] = R(0.25) * (-r11 + r21 - r12 + r22);
-    fa[7] = R(0.25) * (r11 - r21 - r12 + r22);
-    fa[8] = R(0.25) * (-r11 - r21 + r12 + r22);
+    // Inverse of Eq. (6a), added to the incoming populations.
+    const R v1 = R20 - R22, u1 = Fx - R12;
+    const R v2 = R02 - R22, u2 = Fy - R21;
+    const R s1 = R11 + R22, s2 = R21 + R12;
+    const R t1 = R22 - R11, t2 = R21 - R12;
+    fa[0] = a[0] - (v1 + R02);
+    fa[1] = a[1] + R(0.5) * (v1 + u1);
+    fa[3] = a[3] + R(0.5) * (v1 - u1);
+    fa[2] = a[2] + R(0.5) * (v2 + u2);
+    fa[4] = a[4] + R(0.5) * (v2 - u2);
+    fa[5] = a[5] + R(0.25) * (s1 + s2);
+    fa[7] = a[7] + R(0.25) * (s1 - s2);
+    fa[6] = a[6] + R(0.25) * (t1 + t2);
+    fa[8] = a[8] + R(0.25) * (t1 - t2);
 
     if constexpr (VH) {
         const R Qn = (R)c.Q + dissipation<R>(c.vh_pre, c11, n20 - n02, rho);

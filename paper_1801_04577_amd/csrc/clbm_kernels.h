@@ -177,17 +177,18 @@ __device__ __forceinline__ void gather_node(const S* __restrict__ src, const Lat
 
 // Round the post-collision state of one node into the storage type: the deviations,
 // computed wider than the storage, go through the unbiased rounding of sr_round. One
-// hash per node mixes the bits of all 14 results; the k-th value takes
-// h + k * 0x9E3779B9 (a Weyl sequence), each uniform on its own.
+// hash per node mixes the sum of the bits of all 14 results (equal results do not
+// cancel in a sum); the k-th value takes h + k * 0x9E3779B9 (a Weyl sequence), each
+// uniform on its own.
 template <typename S>
 __device__ __forceinline__ void round_node(const typename Wide<S>::type fa[9],
                                            const typename Wide<S>::type tb[5], S out[14])
 {
     unsigned acc = 0;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) acc = ((acc << 5) | (acc >> 27)) ^ hash_bits(fa[i]);
+    for (int i = 0; i < 9; ++i) acc += hash_bits(fa[i]);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) acc = ((acc << 5) | (acc >> 27)) ^ hash_bits(tb[i]);
+    for (int i = 0; i < 5; ++i) acc += hash_bits(tb[i]);
     const unsigned h = mix32(acc);
 #pragma unroll
     for (int i = 0; i < 9; ++i) out[i] = sr_round(fa[i], h + (unsigned)i * 0x9E3779B9u);
@@ -339,11 +340,17 @@ __device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeC
 
 template <typename S, bool VH, int TY, int NT>
 __global__ void __launch_bounds__(NT) k_step2(const S* __restrict__ src, S* __restrict__ dst,
-                                              const LatticeConst c, int tiles_x)
+                                              const LatticeConst c, int tiles_x, int tiles_total,
+                                              int remap)
 {
     __shared__ S tile[14 * Tile2<TY>::P];
-    const int X0 = (int)(blockIdx.x % (unsigned)tiles_x) * (int)kBlock;
-    const int Y0 = (int)(blockIdx.x / (unsigned)tiles_x) * TY;
+    // With remap, each XCD takes a contiguous run of tiles, so the ring nodes a tile
+    // shares with the previous tile of its row (and of the row of tiles above) are
+    // still in that XCD's L2.
+    const int t = tile_of_block(tiles_total, remap);
+    if (t >= tiles_total) return;
+    const int X0 = (t % tiles_x) * (int)kBlock;
+    const int Y0 = (t / tiles_x) * TY;
     step2_phase1<S, VH, TY, NT>(src, c, tile, X0, Y0, (int)threadIdx.x);
     __syncthreads();
     step2_phase2<S, VH, TY, NT>(dst, c, tile, X0, Y0, (int)threadIdx.x);

@@ -103,14 +103,14 @@ LatticeConst make_const(const clbm_params* p, const Rates& r)
     c.periodic_x = p->side[0].kind == CLBM_PERIODIC;
     c.periodic_y = p->side[2].kind == CLBM_PERIODIC;
     const double sp = 0.5 * (r.s_b + r.s_nu), sm = 0.5 * (r.s_b - r.s_nu);
-    c.one_m_sp = (float)(1.0 - sp);
+    c.sp = (float)sp;
     c.sm = (float)sm;
-    c.one_m_snu = (float)(1.0 - r.s_nu);
-    c.one_m_s3 = (float)(1.0 - r.s_3);
+    c.snu = (float)r.s_nu;
+    c.s3 = (float)r.s_3;
     c.half_s3c = (float)((1.0 - 0.5 * r.s_3) / 3.0);
-    c.one_m_s4 = (float)(1.0 - r.s_4);
-    c.one_m_l1 = (float)(1.0 - r.l1);
-    c.one_m_l2 = (float)(1.0 - r.l2);
+    c.s4 = (float)r.s_4;
+    c.l1 = (float)r.l1;
+    c.l2 = (float)r.l2;
     c.src2 = (float)((1.0 - 0.5 * r.l2) * 0.4 * p->Q);
     c.src2_q = (float)((1.0 - 0.5 * r.l2) * 0.4);
     c.viscous = p->viscous_heating ? 1 : 0;
@@ -209,7 +209,9 @@ static clbm_launch default_launch(int precision)
     L.block_x = 256;
     L.block_y = 1;
     L.rows_per_thread = 1;
-    L.xcd_remap = 0;
+    // FP32 storage: two steps per launch over XCD-ordered tiles (the single step that
+    // ends an odd count then also takes the remap, at no measurable cost)
+    L.xcd_remap = precision == CLBM_FP32 ? 1 : 0;
     L.steps_per_launch = precision == CLBM_FP32 ? 2 : 1;
     return L;
 }
@@ -221,17 +223,20 @@ constexpr int kTwoStepThreads = 512;
 struct Step2Launch {
     const void* fn;
     dim3 grid, block;
-    int tiles_x;
+    int tiles_x, tiles_total, remap;
 };
 
-static Step2Launch plan_step2(const LatticeConst& c)
+static Step2Launch plan_step2(const LatticeConst& c, const clbm_launch& L)
 {
     Step2Launch s;
     s.fn = c.viscous ? reinterpret_cast<const void*>(&k_step2<float, true, kTwoStepRows, kTwoStepThreads>)
                      : reinterpret_cast<const void*>(&k_step2<float, false, kTwoStepRows, kTwoStepThreads>);
     s.tiles_x = (c.nx + (int)kBlock - 1) / (int)kBlock;
     const int tiles_y = (c.ny + kTwoStepRows - 1) / kTwoStepRows;
-    s.grid = dim3((unsigned)(s.tiles_x * tiles_y), 1, 1);
+    s.tiles_total = s.tiles_x * tiles_y;
+    s.remap = L.xcd_remap ? 1 : 0;
+    const int g = s.remap ? (int)align_up((size_t)s.tiles_total, 8) : s.tiles_total;
+    s.grid = dim3((unsigned)g, 1, 1);
     s.block = dim3(kTwoStepThreads, 1, 1);
     return s;
 }
@@ -311,7 +316,7 @@ clbm_status plan_steps(clbm_handle* h, int n, int from, Emit emit)
 {
     const bool two = h->launch.steps_per_launch == 2;
     const StepLaunch s1 = plan_step(h->c, h->p.precision, h->launch);
-    const Step2Launch s2 = plan_step2(h->c);
+    const Step2Launch s2 = plan_step2(h->c, h->launch);
     int cur = from;
     while (n > 0) {
         LaunchArgs a;
@@ -320,7 +325,9 @@ clbm_status plan_steps(clbm_handle* h, int n, int from, Emit emit)
         a.c = h->c;
         if (two && n >= 2) {
             a.a0 = s2.tiles_x;
-            void* args[] = {&a.src, &a.dst, &a.c, &a.a0};
+            a.a1 = s2.tiles_total;
+            a.a2 = s2.remap;
+            void* args[] = {&a.src, &a.dst, &a.c, &a.a0, &a.a1, &a.a2};
             clbm_status st = emit(s2.fn, s2.grid, s2.block, args);
             if (st != CLBM_OK) return st;
             n -= 2;
