@@ -51,7 +51,29 @@ struct LatticeConst {
     float src2_q;              // (1 - lambda_2/2) c_T^2
     float uw[4];               // tangential wall speeds, side order x-, x+, y-, y+
     float a1[4], a2[4], a3[4]; // theta_w = a1 theta_1 + a2 theta_2 + a3  (Eq. 28 in theta = T - T0)
+    // The same collision constants in FP64, for the FP64 collision of FP32 storage (kept
+    // in scalar registers instead of being converted per node).
+    double d_sp, d_sm, d_snu, d_s3, d_h3, d_s4, d_l1, d_l2;
+    double d_src2, d_src2_q, d_Q, d_Fx, d_Fy, d_gb, d_T0, d_vh_pre;
 };
+
+// A collision constant in the arithmetic type R: the FP64 copy for R = double.
+template <typename R> __device__ __forceinline__ R kv(float f, double d);
+template <> __device__ __forceinline__ float kv<float>(float f, double) { return f; }
+template <> __device__ __forceinline__ double kv<double>(float, double d) { return d; }
+
+// 1/x in the arithmetic type: the hardware reciprocal refined by one Newton step (relative
+// error far below the type's rounding for the densities of the lattice, x near 1).
+__device__ __forceinline__ double recip(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float recip(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.f), r);
+}
 
 // Element offset of population 0 of node (x, y); population i is kBlock * i further.
 __device__ __forceinline__ unsigned node_off(const LatticeConst& c, int x, int y)
@@ -139,7 +161,7 @@ template <typename R>
 __device__ __forceinline__ void collide_thermal(const LatticeConst& c, const float b[5], R ux,
                                                 R uy, R Q, R src2, R tb[5])
 {
-    const R T0 = c.T0;
+    const R T0 = kv<R>(c.T0, c.d_T0);
     const R b0 = b[0], b1 = b[1], b2 = b[2], b3 = b[3], b4 = b[4];
     // Raw moments of b (Eq. 16); the rest weights carry [T0, 0, 0, T0 c_T^2, T0 c_T^2].
     const R sb = (b0 + b1) + (b2 + b3) + b4;
@@ -152,10 +174,11 @@ __device__ __forceinline__ void collide_thermal(const LatticeConst& c, const flo
     const R m20 = t20 - R(0.4) * theta - R(2.0) * ux * t10 + ux * ux * K00;
     const R m02 = t02 - R(0.4) * theta - R(2.0) * uy * t01 + uy * uy * K00;
     // Eq. (23): changes of the central moments.
-    const R d10 = -(R)c.l1 * e10;
-    const R d01 = -(R)c.l1 * e01;
-    const R d20 = src2 - (R)c.l2 * m20;
-    const R d02 = src2 - (R)c.l2 * m02;
+    const R l1 = kv<R>(c.l1, c.d_l1), l2 = kv<R>(c.l2, c.d_l2);
+    const R d10 = -l1 * e10;
+    const R d01 = -l1 * e01;
+    const R d20 = src2 - l2 * m20;
+    const R d02 = src2 - l2 * m02;
     // Shift by -u (inverse of Eq. 17) with Delta k00 = Q.
     const R r10 = d10 + ux * Q;
     const R r01 = d01 + uy * Q;
@@ -177,10 +200,11 @@ __device__ __forceinline__ void collide_thermal(const LatticeConst& c, const flo
 // The post-collision moments are (1 - s_nu) times the pre-collision ones (the force term
 // has no second-order central part), hence coef/(1 - s_nu)^2 on stored data.
 template <typename R>
-__device__ __forceinline__ R dissipation(float coef, R c11, R c2d, R rho)
+__device__ __forceinline__ R dissipation(R coef, R c11, R c2d, R rho)
 {
     const R h = R(0.5) * c2d;
-    return (R)coef * (c11 * c11 + h * h) / (rho * rho);
+    const R ir = recip(rho);
+    return coef * (c11 * c11 + h * h) * (ir * ir);
 }
 
 // Cascaded collision of one node. On entry a[9], b[5] hold the pre-collision
@@ -208,8 +232,8 @@ __device__ __forceinline__ void collide(const LatticeConst& c, const float a_in[
     const float sb = (b[0] + b[1]) + (b[2] + b[3]) + b[4];
     const float theta = sb + 0.5f * c.Q;
     // Eq. (2): gravity along -y.
-    const R Fx = c.Fx;
-    const R Fy = (R)c.Fy + (R)c.g_beta * (R)theta;
+    const R Fx = kv<R>(c.Fx, c.d_Fx);
+    const R Fy = kv<R>(c.Fy, c.d_Fy) + kv<R>(c.g_beta, c.d_gb) * (R)theta;
     R a[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) a[i] = a_in[i];
@@ -232,7 +256,7 @@ __device__ __forceinline__ void collide(const LatticeConst& c, const float a_in[
 
     // Eq. (12).
     const R rho = R(1) + d;
-    const R inv = R(1) / rho;
+    const R inv = recip(rho);
     const R ux = (jx + R(0.5) * Fx) * inv;
     const R uy = (jy + R(0.5) * Fy) * inv;
     const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
@@ -250,12 +274,14 @@ __device__ __forceinline__ void collide(const LatticeConst& c, const float a_in[
                   + ux2 * uy2 * rho;
 
     // Eq. (7): changes of the central moments; on k10, k01 the change is the force.
-    const R D20 = -((R)c.sp * n20 + (R)c.sm * n02);
-    const R D02 = -((R)c.sp * n02 + (R)c.sm * n20);
-    const R D11 = -(R)c.snu * c11;
-    const R D21 = (R)c.half_s3c * Fy - (R)c.s3 * c21;
-    const R D12 = (R)c.half_s3c * Fx - (R)c.s3 * c12;
-    const R D22 = -(R)c.s4 * n22;
+    const R sp = kv<R>(c.sp, c.d_sp), sm = kv<R>(c.sm, c.d_sm);
+    const R s3 = kv<R>(c.s3, c.d_s3), h3 = kv<R>(c.half_s3c, c.d_h3);
+    const R D20 = -(sp * n20 + sm * n02);
+    const R D02 = -(sp * n02 + sm * n20);
+    const R D11 = -kv<R>(c.snu, c.d_snu) * c11;
+    const R D21 = h3 * Fy - s3 * c21;
+    const R D12 = h3 * Fx - s3 * c12;
+    const R D22 = -kv<R>(c.s4, c.d_s4) * n22;
 
     // Shift by -u (inverse of Eq. 6b); Delta k00 = 0.
     const R R20 = D20 + R(2) * ux * Fx;
@@ -282,11 +308,11 @@ __device__ __forceinline__ void collide(const LatticeConst& c, const float a_in[
     fa[8] = a[8] + R(0.25) * (t1 - t2);
 
     if constexpr (VH) {
-        const R Qn = (R)c.Q + dissipation<R>(c.vh_pre, c11, n20 - n02, rho);
-        collide_thermal(c, b, ux, uy, Qn, (R)c.src2_q * Qn, tb);
+        const R Qn = kv<R>(c.Q, c.d_Q) + dissipation<R>(kv<R>(c.vh_pre, c.d_vh_pre), c11, n20 - n02, rho);
+        collide_thermal(c, b, ux, uy, Qn, kv<R>(c.src2_q, c.d_src2_q) * Qn, tb);
         m.theta = (float)((R)sb + R(0.5) * Qn);
     } else {
-        collide_thermal(c, b, ux, uy, (R)c.Q, (R)c.src2, tb);
+        collide_thermal(c, b, ux, uy, kv<R>(c.Q, c.d_Q), kv<R>(c.src2, c.d_src2), tb);
         m.theta = theta;
     }
     m.drho = (float)d;

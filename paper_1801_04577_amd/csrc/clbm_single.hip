@@ -111,12 +111,28 @@ LatticeConst make_const(const clbm_params* p, const Rates& r)
     c.s4 = (float)r.s_4;
     c.l1 = (float)r.l1;
     c.l2 = (float)r.l2;
+    c.d_sp = sp;
+    c.d_sm = sm;
+    c.d_snu = r.s_nu;
+    c.d_s3 = r.s_3;
+    c.d_h3 = (1.0 - 0.5 * r.s_3) / 3.0;
+    c.d_s4 = r.s_4;
+    c.d_l1 = r.l1;
+    c.d_l2 = r.l2;
+    c.d_src2 = (1.0 - 0.5 * r.l2) * 0.4 * p->Q;
+    c.d_src2_q = (1.0 - 0.5 * r.l2) * 0.4;
+    c.d_Q = p->Q;
+    c.d_Fx = p->Fx;
+    c.d_Fy = p->Fy;
+    c.d_gb = p->g_beta;
+    c.d_T0 = p->T0;
     c.src2 = (float)((1.0 - 0.5 * r.l2) * 0.4 * p->Q);
     c.src2_q = (float)((1.0 - 0.5 * r.l2) * 0.4);
     c.viscous = p->viscous_heating ? 1 : 0;
     if (c.viscous) {
         const double coef = 9.0 * p->nu * r.s_nu * r.s_nu;
         c.vh_pre = (float)coef;
+        c.d_vh_pre = coef;
         c.vh_post = (float)(coef / ((1.0 - r.s_nu) * (1.0 - r.s_nu)));
     }
     c.g_beta = (float)p->g_beta;
