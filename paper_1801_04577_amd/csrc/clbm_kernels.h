@@ -311,7 +311,9 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
         for (int i = 0; i < 14; ++i) tile[i * T::P + o] = v[i];
     };
     // one wave per row for the kBlock interior columns, then the two ring columns
-    for (int ly = wave; ly < T::YE; ly += nwaves) advance(lane + 1, ly);
+    static_assert(T::YE % nwaves == 0, "rows of the tile and ring per wave");
+#pragma unroll
+    for (int k = 0; k < T::YE / nwaves; ++k) advance(lane + 1, wave + k * nwaves);
     for (int k = tid; k < 2 * T::YE; k += NT) advance(k < T::YE ? 0 : T::XE - 1, k % T::YE);
 }
 
@@ -326,9 +328,10 @@ __device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeC
     const TileMem<S, TY> mem{tile, X0 - 1, Y0 - 1};
     const int gx = X0 + lane;
     if (gx >= c.nx) return;
-    for (int ly = wave; ly < TY; ly += nwaves) {
-        const int gy = Y0 + ly;
-        if (gy >= c.ny) break;
+#pragma unroll
+    for (int k = 0; k < (TY + nwaves - 1) / nwaves; ++k) {
+        const int ly = wave + k * nwaves, gy = Y0 + ly;
+        if (ly >= TY || gy >= c.ny) break;
         float a[9], b[5];
         W fa[9], tb[5];
         NodeMacro m;
