@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define CLBM_ABI_VERSION 4
+#define CLBM_ABI_VERSION 5
 
 typedef enum {
     CLBM_OK = 0,
@@ -209,12 +209,16 @@ typedef struct clbm_batch clbm_batch;
 enum { CLBM_INST_RUNNING = 0, CLBM_INST_CONVERGED = 1, CLBM_INST_DIVERGED = 2,
        CLBM_INST_MAX_STEPS = 3 };
 
-/* Tile shape of the batched kernel: tile_x * tile_y nodes per workgroup, one node
- * per thread (tile_x a multiple of 64, tile_x * tile_y <= 1024). persistent_wgs > 0
- * launches that many workgroups, each looping over tiles; 0 launches one workgroup
- * per tile. */
+/* Tile shape of the batched kernel. steps_per_launch = 1: tile_x * tile_y nodes per
+ * workgroup, one node per thread (tile_x a multiple of 64, tile_x * tile_y <= 1024).
+ * steps_per_launch = 2: two time steps per launch with the intermediate state in LDS,
+ * tiles of exactly 64 x 14 nodes (tile_x = 64, tile_y = 14), 512 threads; bitwise equal
+ * to one-step launches. persistent_wgs > 0 launches that many workgroups, each looping
+ * over tiles; 0 launches one workgroup per tile. The default (launch NULL at create)
+ * is the two-step shape with one workgroup per tile. */
 typedef struct {
     int tile_x, tile_y, persistent_wgs;
+    int steps_per_launch;
 } clbm_batch_launch;
 
 /* Host only. Workspace for n instances (all precision fields must be CLBM_FP32). */

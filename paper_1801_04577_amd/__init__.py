@@ -83,7 +83,8 @@ class clbm_problem_code(ctypes.Structure):
 
 
 class clbm_batch_launch(ctypes.Structure):
-    _fields_ = [("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int), ("persistent_wgs", ctypes.c_int)]
+    _fields_ = [("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int), ("persistent_wgs", ctypes.c_int),
+                ("steps_per_launch", ctypes.c_int)]
 
 
 _lib = None
@@ -385,7 +386,8 @@ class Batch:
         L = None
         if launch:
             L = clbm_batch_launch(int(launch["tile_x"]), int(launch["tile_y"]),
-                                  int(launch.get("persistent_wgs", 0)))
+                                  int(launch.get("persistent_wgs", 0)),
+                                  int(launch.get("steps_per_launch", 1)))
         h = ctypes.c_void_p()
         _check(lib().clbm_batch_create(self.n, self.params, _addr(self.workspace),
                                        self.workspace.numel(), _stream_ptr(self.stream),
@@ -447,8 +449,8 @@ class Batch:
         _check(lib().clbm_batch_residual(self._h, int(i), out), "clbm_batch_residual")
         return out[0], out[1]
 
-    def set_launch(self, tile_x, tile_y, persistent_wgs=0):
-        L = clbm_batch_launch(int(tile_x), int(tile_y), int(persistent_wgs))
+    def set_launch(self, tile_x, tile_y, persistent_wgs=0, steps_per_launch=1):
+        L = clbm_batch_launch(int(tile_x), int(tile_y), int(persistent_wgs), int(steps_per_launch))
         _check(lib().clbm_batch_set_launch(self._h, ctypes.byref(L)), "clbm_batch_set_launch")
 
     def autotune(self, steps=20, cache_path=None):
@@ -456,7 +458,8 @@ class Batch:
         path = cache_path.encode() if cache_path else None
         _check(lib().clbm_batch_autotune(self._h, int(steps), path, ctypes.byref(best)),
                "clbm_batch_autotune")
-        return {"tile_x": best.tile_x, "tile_y": best.tile_y, "persistent_wgs": best.persistent_wgs}
+        return {"tile_x": best.tile_x, "tile_y": best.tile_y, "persistent_wgs": best.persistent_wgs,
+                "steps_per_launch": best.steps_per_launch}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

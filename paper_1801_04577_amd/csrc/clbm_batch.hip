@@ -61,6 +61,44 @@ __global__ void __launch_bounds__(1024) k_batch_step(const BatchInst* __restrict
     }
 }
 
+// Two time steps of every instance on the active tile list (tiles of kBlock x
+// kTwoStepRows nodes, grid-stride over tiles; the LDS tile is reused by each tile a
+// workgroup takes). Per tile it runs the phases of k_step2, so two steps here are two
+// steps of k_batch_step bit for bit. VH: 0 = no instance has viscous heating, 1 = all
+// have, 2 = mixed (both paths compiled in; the register budget is held at two
+// workgroups per CU).
+template <int VH>
+__global__ void __launch_bounds__(kTwoStepThreads) __attribute__((amdgpu_waves_per_eu(4))) k_batch_step2(const BatchInst* __restrict__ insts,
+                                                                    const int2* __restrict__ list,
+                                                                    const int* __restrict__ count,
+                                                                    int parity)
+{
+    constexpr int TY = kTwoStepRows, NT = kTwoStepThreads;
+    __shared__ float tile[14 * Tile2<TY>::P];
+    const int n = uniform_int(*count);
+    const int tid = (int)threadIdx.x;
+    for (int t = blockIdx.x; t < n; t += gridDim.x) {
+        const int2 e = list[t];
+        const int inst = uniform_int(e.x), id = uniform_int(e.y);
+        const BatchInst& I = insts[inst];
+        const LatticeConst c = I.c;
+        const int tiles_x = uniform_int(I.tiles_x);
+        const int X0 = (id % tiles_x) * (int)kBlock, Y0 = (id / tiles_x) * TY;
+        const float* src = reinterpret_cast<const float*>(I.buf[parity]);
+        float* dst = reinterpret_cast<float*>(I.buf[parity ^ 1]);
+        if (VH == 1 || (VH == 2 && c.viscous)) {
+            step2_phase1<float, true, TY, NT>(src, c, tile, X0, Y0, tid);
+            __syncthreads();
+            step2_phase2<float, true, TY, NT>(dst, c, tile, X0, Y0, tid);
+        } else {
+            step2_phase1<float, false, TY, NT>(src, c, tile, X0, Y0, tid);
+            __syncthreads();
+            step2_phase2<float, false, TY, NT>(dst, c, tile, X0, Y0, tid);
+        }
+        __syncthreads();  // the next tile overwrites the LDS tile
+    }
+}
+
 __device__ __forceinline__ double wave_sum_d(double v)
 {
 #pragma unroll
@@ -284,16 +322,19 @@ struct BatchLayout {
 
 bool batch_launch_ok(const clbm_batch_launch& L)
 {
-    return L.tile_x >= kMinTileX && L.tile_x % 64 == 0 && L.tile_y >= 1 &&
-           L.tile_x * L.tile_y <= 1024 && L.persistent_wgs >= 0;
+    if (L.persistent_wgs < 0) return false;
+    if (L.steps_per_launch == 2) return L.tile_x == (int)kBlock && L.tile_y == kTwoStepRows;
+    if (L.steps_per_launch != 1) return false;
+    return L.tile_x >= kMinTileX && L.tile_x % 64 == 0 && L.tile_y >= 1 && L.tile_x * L.tile_y <= 1024;
 }
 
 clbm_batch_launch default_batch_launch()
 {
     clbm_batch_launch L;
-    L.tile_x = 64;
-    L.tile_y = 4;
+    L.tile_x = (int)kBlock;
+    L.tile_y = kTwoStepRows;
     L.persistent_wgs = 0;
+    L.steps_per_launch = 2;
     return L;
 }
 
@@ -402,15 +443,35 @@ clbm_status add_node(hipGraph_t g, hipGraphNode_t* prev, const void* fn, dim3 gr
     return CLBM_OK;
 }
 
+// The two-step kernel for the batch's mix of instances with and without viscous heating.
+const void* step2_kernel(const clbm_batch* b)
+{
+    int vh = 0;
+    for (int i = 0; i < b->n; ++i) vh += b->p[i].viscous_heating ? 1 : 0;
+    if (vh == 0) return reinterpret_cast<const void*>(&k_batch_step2<0>);
+    if (vh == b->n) return reinterpret_cast<const void*>(&k_batch_step2<1>);
+    return reinterpret_cast<const void*>(&k_batch_step2<2>);
+}
+
 clbm_status launch_batch_steps(clbm_batch* b, int nsteps)
 {
     const dim3 blk(b->launch.tile_x, b->launch.tile_y);
-    for (int k = 0; k < nsteps; ++k) {
-        hipLaunchKernelGGL(k_batch_step, step_grid(b), blk, 0, b->stream, b->d_inst, b->d_active,
-                           b->d_count, b->parity, b->launch.tile_x, b->launch.tile_y);
+    while (nsteps > 0) {
+        if (b->launch.steps_per_launch == 2 && nsteps >= 2) {
+            int parity = b->parity;
+            void* args[] = {&b->d_inst, &b->d_active, &b->d_count, &parity};
+            CLBM_HIP(hipLaunchKernel(step2_kernel(b), step_grid(b), dim3(kTwoStepThreads), args, 0,
+                                     b->stream));
+            b->step += 2;
+            nsteps -= 2;
+        } else {
+            hipLaunchKernelGGL(k_batch_step, step_grid(b), blk, 0, b->stream, b->d_inst, b->d_active,
+                               b->d_count, b->parity, b->launch.tile_x, b->launch.tile_y);
+            b->step += 1;
+            nsteps -= 1;
+        }
         CLBM_HIP(hipGetLastError());
         b->parity ^= 1;
-        b->step++;
     }
     return CLBM_OK;
 }
@@ -436,7 +497,20 @@ clbm_status build_run_graph(clbm_batch* b, int K, double tol, long max_steps)
     int parity = b->parity;
     int tx = b->launch.tile_x, ty = b->launch.tile_y;
     clbm_status st = CLBM_OK;
-    for (int k = 0; k < K && st == CLBM_OK; ++k) {
+    // The graph is replayed from the same buffer, so it must flip the buffers an even
+    // number of times: K one-step launches, or two-step launches with two one-step
+    // launches in place of one of them when K/2 is odd.
+    int pairs = 0, singles = K;
+    if (b->launch.steps_per_launch == 2) {
+        pairs = (K / 2) % 2 == 0 ? K / 2 : K / 2 - 1;
+        singles = K - 2 * pairs;
+    }
+    for (int k = 0; k < pairs && st == CLBM_OK; ++k) {
+        void* args[] = {&b->d_inst, &b->d_active, &b->d_count, &parity};
+        st = add_node(g, &prev, step2_kernel(b), grid, dim3(kTwoStepThreads), args);
+        parity ^= 1;
+    }
+    for (int k = 0; k < singles && st == CLBM_OK; ++k) {
         void* args[] = {&b->d_inst, &b->d_active, &b->d_count, &parity, &tx, &ty};
         st = add_node(g, &prev, reinterpret_cast<const void*>(&k_batch_step), grid, blk, args);
         parity ^= 1;
@@ -685,8 +759,10 @@ clbm_status clbm_batch_autotune(clbm_batch* b, int steps, const char* cache_path
                                 clbm_batch_launch* best)
 {
     if (!b || steps < 1) return CLBM_ERR_INVALID_ARG;
-    static const int shapes[][2] = {{64, 1}, {64, 2}, {64, 4}, {64, 8}, {128, 1}, {128, 2},
-                                    {128, 4}, {256, 1}, {256, 2}, {256, 4}, {512, 1}, {512, 2}};
+    // {tile_x, tile_y, steps per launch}
+    static const int shapes[][3] = {{64, 1, 1}, {64, 2, 1}, {64, 4, 1}, {64, 8, 1}, {128, 1, 1},
+                                    {128, 2, 1}, {128, 4, 1}, {256, 1, 1}, {256, 2, 1}, {256, 4, 1},
+                                    {512, 1, 1}, {512, 2, 1}, {(int)kBlock, kTwoStepRows, 2}};
     static const int wgs[] = {0, 2048, 8192};
     FILE* fp = cache_path ? std::fopen(cache_path, "a") : nullptr;
     hipEvent_t e0, e1;
@@ -702,6 +778,7 @@ clbm_status clbm_batch_autotune(clbm_batch* b, int steps, const char* cache_path
             clbm_batch_launch L;
             L.tile_x = sh[0];
             L.tile_y = sh[1];
+            L.steps_per_launch = sh[2];
             L.persistent_wgs = w;
             if (!batch_launch_ok(L)) continue;
             b->launch = L;
@@ -720,9 +797,10 @@ clbm_status clbm_batch_autotune(clbm_batch* b, int steps, const char* cache_path
             const double per = ms / (2 * ((steps + 1) / 2));
             if (fp)
                 std::fprintf(fp, "{\"tile_x\": %d, \"tile_y\": %d, \"persistent_wgs\": %d, "
+                                 "\"steps_per_launch\": %d, "
                                  "\"instances\": %d, \"nodes\": %lld, \"ms_per_step\": %.6f, "
                                  "\"mlups\": %.1f}\n",
-                             L.tile_x, L.tile_y, L.persistent_wgs, b->n, nodes, per,
+                             L.tile_x, L.tile_y, L.persistent_wgs, L.steps_per_launch, b->n, nodes, per,
                              nodes / (per * 1e-3) / 1e6);
             if (per < best_ms) {
                 best_ms = per;

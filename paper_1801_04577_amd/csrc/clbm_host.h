@@ -25,6 +25,10 @@ void set_last_hip_error(hipError_t e, const char* what, const char* file, int li
 
 constexpr size_t kAlign = 256;   // workspace region alignment, bytes
 
+// Two steps per launch: tiles of kBlock x kTwoStepRows nodes, kTwoStepThreads threads.
+constexpr int kTwoStepRows = 14;
+constexpr int kTwoStepThreads = 512;
+
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Rates {

@@ -327,17 +327,18 @@ __device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeC
     constexpr int nwaves = NT / 64;
     const TileMem<S, TY> mem{tile, X0 - 1, Y0 - 1};
     const int gx = X0 + lane;
-    if (gx >= c.nx) return;
+    if (gx < c.nx) {
 #pragma unroll
-    for (int k = 0; k < (TY + nwaves - 1) / nwaves; ++k) {
-        const int ly = wave + k * nwaves, gy = Y0 + ly;
-        if (ly >= TY || gy >= c.ny) break;
-        float a[9], b[5];
-        W fa[9], tb[5];
-        NodeMacro m;
-        gather_mem<VH>(mem, c, gx, gy, a, b);
-        collide<W, VH>(c, a, b, fa, tb, m);
-        store_node(dst, c, node_off(c, gx, gy), fa, tb);
+        for (int k = 0; k < (TY + nwaves - 1) / nwaves; ++k) {
+            const int ly = wave + k * nwaves, gy = Y0 + ly;
+            if (ly >= TY || gy >= c.ny) break;
+            float a[9], b[5];
+            W fa[9], tb[5];
+            NodeMacro m;
+            gather_mem<VH>(mem, c, gx, gy, a, b);
+            collide<W, VH>(c, a, b, fa, tb, m);
+            store_node(dst, c, node_off(c, gx, gy), fa, tb);
+        }
     }
 }
 

@@ -232,10 +232,6 @@ static clbm_launch default_launch(int precision)
     return L;
 }
 
-// Two steps per launch (FP32 storage): tiles of kBlock x kTwoStepRows nodes.
-constexpr int kTwoStepRows = 14;
-constexpr int kTwoStepThreads = 512;
-
 struct Step2Launch {
     const void* fn;
     dim3 grid, block;

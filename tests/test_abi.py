@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_abi_version(L):
-    assert clbm.clbm_abi_version() == 4
+    assert clbm.clbm_abi_version() == 5
 
 
 PROBLEMS = [

@@ -45,7 +45,9 @@ def run_single(prob, fields, steps):
 
 
 @pytest.mark.parametrize("launch", [None, dict(tile_x=128, tile_y=2, persistent_wgs=0),
-                                    dict(tile_x=64, tile_y=8, persistent_wgs=64)])
+                                    dict(tile_x=64, tile_y=8, persistent_wgs=64),
+                                    dict(tile_x=64, tile_y=14, persistent_wgs=0, steps_per_launch=2),
+                                    dict(tile_x=64, tile_y=14, persistent_wgs=40, steps_per_launch=2)])
 def test_batch_equals_single_lattices(launch):
     import torch
     import paper_1801_04577_amd as clbm
@@ -98,6 +100,29 @@ def test_batch_run_converges_and_retires():
     # frozen after retirement: a second run with tol=inf retires everything after one window
     s2, st2 = b.run(max_steps=1000, tol=float("inf"), K=200)
     assert st2 == ["converged"] * 3 and s2 == [200] * 3
+
+
+@pytest.mark.parametrize("K", [150, 200])
+def test_batch_run_two_step_equals_one_step(K):
+    """The replayed run graph with two-step launches (K/2 odd: two one-step launches
+    keep the buffer parity) ends in the same states, step counts and statuses as the
+    one-step graph."""
+    import torch
+    import paper_1801_04577_amd as clbm
+    probs = [W.cavity(24, 24, Ra=1e3, Pr=0.71), W.cavity(70, 33, Ra=1e4, Pr=0.71, Q=1e-5),
+             dict(W.viscous_channel(20, nx=66), Q=1e-6)]
+    out = []
+    for launch in (dict(tile_x=64, tile_y=4, steps_per_launch=1),
+                   dict(tile_x=64, tile_y=14, steps_per_launch=2)):
+        b = clbm.Batch(probs, launch=launch)
+        for i, p in enumerate(probs):
+            b.init(i, T=torch.from_numpy(f32(p["T0"] + W.noise_field(i, p["nx"], p["ny"], 1e-4))))
+        steps, status = b.run(max_steps=3 * K, tol=1e-12, K=K)
+        out.append((steps, status, [b.macros(i) for i in range(len(probs))]))
+    assert out[0][0] == out[1][0] and out[0][1] == out[1][1]
+    for ma, mb in zip(out[0][2], out[1][2]):
+        for x, y in zip(ma, mb):
+            assert torch.equal(x, y)
 
 
 def test_batch_divergence_and_max_steps():
