@@ -50,49 +50,74 @@ __device__ __forceinline__ bf16 f2bf(float v) { return (bf16)v; }
 // mode 0: y = bf16(relu(acc + bias)); mode 1: y = bf16(acc) (input gradients);
 // mode 2: fp32 NCHW output yf = acc + bias (network output, n < N only).
 // ---------------------------------------------------------------------------
-template <int NB>
+template <int NB, int MP>
 __global__ void __launch_bounds__(256) k_conv(const bf16* __restrict__ x, int xC, int xoff, int Cin,
                                               const bf16* __restrict__ w,
                                               const float* __restrict__ bias, int N, int H, int W,
                                               int mode, bf16* __restrict__ y, int yC, int yoff,
                                               float* __restrict__ yf)
 {
+    // A wave owns MP blocks of 16 pixels and NB blocks of 16 output channels: per tap and
+    // 32-channel chunk it loads MP activation and NB weight fragments and issues MP x NB
+    // MFMAs, each fragment reused NB (or MP) times from registers.
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int HW = H * W;
-    const int p0 = blockIdx.x * 64 + wave * 16;
+    const int p0 = (blockIdx.x * 4 + wave) * 16 * MP;
     const int n0 = blockIdx.y * (16 * NB);
-    const int pa = p0 + (lane & 15);
-    const int b = pa / HW, rem = pa - b * HW, py = rem / W, px = rem - py * W;
     const int kq = (lane >> 4) * 8;
-    f32x4 acc[NB];
+    int pb[MP], py[MP], px[MP];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < MP; ++j) {
+        const int pa = p0 + 16 * j + (lane & 15);
+        pb[j] = pa / HW;
+        const int rem = pa - pb[j] * HW;
+        py[j] = rem / W;
+        px[j] = rem - py[j] * W;
+    }
+    f32x4 acc[MP][NB];
+#pragma unroll
+    for (int j = 0; j < MP; ++j)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[j][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero = {};
     for (int tap = 0; tap < 9; ++tap) {
-        const int sy = py + tap / 3 - 1, sx = px + tap % 3 - 1;
-        const bool in = sy >= 0 && sy < H && sx >= 0 && sx < W;
-        // clamped source so the address is valid even where the value is not used
-        const int cy = min(max(sy, 0), H - 1), cx = min(max(sx, 0), W - 1);
-        const bf16* xs = x + (size_t)(b * HW + cy * W + cx) * xC + xoff + kq;
+        const bf16* xs[MP];
+        bool in[MP];
+#pragma unroll
+        for (int j = 0; j < MP; ++j) {
+            const int sy = py[j] + tap / 3 - 1, sx = px[j] + tap % 3 - 1;
+            in[j] = sy >= 0 && sy < H && sx >= 0 && sx < W;
+            // clamped source so the address is valid even where the value is not used
+            const int cy = min(max(sy, 0), H - 1), cx = min(max(sx, 0), W - 1);
+            xs[j] = x + (size_t)(pb[j] * HW + cy * W + cx) * xC + xoff + kq;
+        }
         for (int c0 = 0; c0 < Cin; c0 += kKChunk) {
-            bf16x8 a = *reinterpret_cast<const bf16x8*>(xs + c0);
-            if (!in) a = zero;
+            bf16x8 a[MP];
+#pragma unroll
+            for (int j = 0; j < MP; ++j) {
+                a[j] = *reinterpret_cast<const bf16x8*>(xs[j] + c0);
+                if (!in[j]) a[j] = zero;
+            }
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const int n = n0 + 16 * nb + (lane & 15);
                 const bf16x8 bw =
                     *reinterpret_cast<const bf16x8*>(w + ((size_t)n * 9 + tap) * Cin + c0 + kq);
-                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[nb], 0, 0, 0);
+#pragma unroll
+                for (int j = 0; j < MP; ++j)
+                    acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j], bw, acc[j][nb], 0, 0, 0);
             }
         }
     }
+#pragma unroll
+    for (int j = 0; j < MP; ++j)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         const int n = n0 + 16 * nb + (lane & 15);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int p = p0 + 4 * (lane >> 4) + v;
-            float r = acc[nb][v];
+            const int p = p0 + 16 * j + 4 * (lane >> 4) + v;
+            float r = acc[j][nb][v];
             if (mode == 2) {
                 if (n < N) {
                     const int bb = p / HW, rr = p - bb * HW;
@@ -629,10 +654,16 @@ clbm_status conv_launch(clbm_net* n, const Layer& l, TView in, int cin_pad, cons
                         const float* bias, int N, int nb, int npad, int mode, TView out, float* yf)
 {
     const int P = n->d.batch * l.H * l.W;
-    const dim3 grid(P / 64, npad / (16 * nb));
-    const void* fn = nb == 4 ? reinterpret_cast<const void*>(&k_conv<4>)
-                   : nb == 2 ? reinterpret_cast<const void*>(&k_conv<2>)
-                             : reinterpret_cast<const void*>(&k_conv<1>);
+    // four 16-pixel blocks per wave where the pixel count allows (it is a multiple of 64)
+    const int mp = P % 256 == 0 ? 4 : 1;
+    const dim3 grid(P / (64 * mp), npad / (16 * nb));
+    const void* fn =
+        mp == 4 ? (nb == 4 ? reinterpret_cast<const void*>(&k_conv<4, 4>)
+                  : nb == 2 ? reinterpret_cast<const void*>(&k_conv<2, 4>)
+                            : reinterpret_cast<const void*>(&k_conv<1, 4>))
+                : (nb == 4 ? reinterpret_cast<const void*>(&k_conv<4, 1>)
+                  : nb == 2 ? reinterpret_cast<const void*>(&k_conv<2, 1>)
+                            : reinterpret_cast<const void*>(&k_conv<1, 1>));
     int xC = in.C, xoff = in.off, Cin = cin_pad, H = l.H, W = l.W, yC = out.C, yoff = out.off;
     const bf16* x = in.p;
     bf16* y = out.p;
