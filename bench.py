@@ -4,9 +4,12 @@ Workload: the 4096 x 4096 differentially heated cavity (Ra = 1e6, Pr = 0.71,
 uniform heat source Q = 5e-6, Dirichlet side walls, adiabatic top and bottom,
 U = 0.1), FP32 populations. This is the configuration whose working set
 (1.88 GB of populations) exceeds the 256 MB Infinity Cache, so its HBM
-roofline fraction is meaningful. One step = one launch of the fused
-collide-and-stream kernel; the diagnostics reduction (residual, wall heat flux,
-mass, NaN check) runs every --diag-every steps inside the timed region.
+roofline fraction is meaningful. One step = one collide-and-stream update of
+every node; the FP32 default launch advances two steps per kernel launch
+(k_step2, the first step's tile and halo kept in LDS), so the roofline's
+algorithmic bytes per launch are 112 B x nodes x 2. The diagnostics reduction
+(residual, wall heat flux, mass, NaN check) runs every --diag-every steps inside
+the timed region.
 
 Prints one JSON line: MLUPS (million lattice-node updates per second, both
 distributions), the roofline of the step kernel (algorithmic 112 B per node
