@@ -208,6 +208,79 @@ __device__ __forceinline__ void store_node(S* __restrict__ dst, const LatticeCon
     for (int i = 0; i < 14; ++i) st_nt(dst + i * kBlock + own, v[i]);
 }
 
+// Store the post-collision state of one node given the address of its population 0.
+template <typename S>
+__device__ __forceinline__ void store_node_at(S* __restrict__ p0, const typename Wide<S>::type fa[9],
+                                              const typename Wide<S>::type tb[5])
+{
+    S v[14];
+    round_node<S>(fa, tb, v);
+#pragma unroll
+    for (int i = 0; i < 14; ++i) st_nt(p0 + i * kBlock, v[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Interior nodes. Where a node and the nodes it pulls from all lie strictly inside the
+// lattice, no link crosses a wall and no neighbour wraps, so the gather needs neither the
+// wall substitutions nor the wrapped offsets. Its sources are then addressed as a row
+// pointer (uniform across a wave when the wave works on one row) plus a per-thread byte
+// offset of the column, which the loads take as scalar base + 32-bit offset + immediate.
+// ---------------------------------------------------------------------------
+
+// Byte offsets, within a row, of the columns x-1, x and x+1.
+struct ColBytes {
+    unsigned m, c, p;
+};
+
+// Columns of the stored layout: population 0 of x sits at (x/kBlock)*kBlockElems + x%kBlock,
+// so stepping across a block boundary jumps kBlockElems - kBlock + 1 elements.
+template <typename S>
+__device__ __forceinline__ ColBytes stored_cols(int x)
+{
+    const unsigned e = (unsigned)sizeof(S);
+    const unsigned xb = (unsigned)x % kBlock;
+    const unsigned cc = (((unsigned)x / kBlock) * kBlockElems + xb) * e;
+    const unsigned jump = (kBlockElems - kBlock + 1) * e;
+    return ColBytes{xb == 0 ? cc - jump : cc - e, cc, xb == kBlock - 1 ? cc + jump : cc + e};
+}
+
+// Start of stored row y.
+template <typename S>
+__device__ __forceinline__ const char* stored_row(const S* p, unsigned rowlen, int y)
+{
+    return reinterpret_cast<const char*>(p) + (size_t)(unsigned)y * rowlen * sizeof(S);
+}
+template <typename S>
+__device__ __forceinline__ char* stored_row(S* p, unsigned rowlen, int y)
+{
+    return reinterpret_cast<char*>(p) + (size_t)(unsigned)y * rowlen * sizeof(S);
+}
+
+// Pull gather (Eq. 11, Eq. 21) of an interior node from the rows y-1 (rm), y (rc), y+1 (rp)
+// of the post-collision populations at time t; P is the population stride in elements.
+template <typename S, unsigned P>
+__device__ __forceinline__ void gather_interior(const char* rm, const char* rc, const char* rp,
+                                                const ColBytes k, float a[9], float b[5])
+{
+    auto at = [&](const char* row, unsigned col, int i) {
+        return ld(reinterpret_cast<const S*>(row + col) + i * P);
+    };
+    a[0] = at(rc, k.c, 0);
+    a[1] = at(rc, k.m, 1);
+    a[2] = at(rm, k.c, 2);
+    a[3] = at(rc, k.p, 3);
+    a[4] = at(rp, k.c, 4);
+    a[5] = at(rm, k.m, 5);
+    a[6] = at(rm, k.p, 6);
+    a[7] = at(rp, k.p, 7);
+    a[8] = at(rp, k.m, 8);
+    b[0] = at(rc, k.c, 9);
+    b[1] = at(rc, k.m, 10);
+    b[2] = at(rm, k.c, 11);
+    b[3] = at(rc, k.p, 12);
+    b[4] = at(rp, k.c, 13);
+}
+
 // Tile -> workgroup map. With xcd_remap the grid is padded to a multiple of 8 and
 // workgroup b (dispatched to XCD b % 8) takes tile (b % 8) * (grid/8) + b/8, so
 // each XCD sweeps one contiguous band of tiles.
@@ -224,21 +297,42 @@ __global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __r
                                                const LatticeConst c, int tiles_x, int tiles_total,
                                                int remap)
 {
+    typedef typename Wide<S>::type W;
     const int t = tile_of_block(tiles_total, remap);
     if (t >= tiles_total) return;
     const int tx = t % tiles_x, ty = t / tiles_x;
     const int x = tx * blockDim.x + threadIdx.x;
     const int y0 = (ty * blockDim.y + threadIdx.y) * ROWS;
+    // A block whose nodes and their sources all lie strictly inside the lattice takes the
+    // interior gather when each wave covers one row (rows are then wave-uniform).
+    const int bx0 = tx * (int)blockDim.x, by0 = ty * (int)blockDim.y * ROWS;
+    if (blockDim.x % 64 == 0 && bx0 >= 1 && bx0 + (int)blockDim.x < c.nx && by0 >= 1
+        && by0 + (int)blockDim.y * ROWS < c.ny) {
+        const ColBytes k = stored_cols<S>(x);
+        const int yw = __builtin_amdgcn_readfirstlane(y0);
+        const size_t rb = (size_t)c.rowlen * sizeof(S);
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const char* rc = stored_row(src, c.rowlen, yw + r);
+            float a[9], b[5];
+            W fa[9], tb[5];
+            NodeMacro m;
+            gather_interior<S, kBlock>(rc - rb, rc, rc + rb, k, a, b);
+            collide<W, VH>(c, a, b, fa, tb, m);
+            store_node_at(reinterpret_cast<S*>(stored_row(dst, c.rowlen, yw + r) + k.c), fa, tb);
+        }
+        return;
+    }
     if (x >= c.nx) return;
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         const int y = y0 + r;
         if (y < c.ny) {
             float a[9], b[5];
-            typename Wide<S>::type fa[9], tb[5];
+            W fa[9], tb[5];
             gather_node<S, VH>(src, c, x, y, a, b);
             NodeMacro m;
-            collide<typename Wide<S>::type, VH>(c, a, b, fa, tb, m);
+            collide<W, VH>(c, a, b, fa, tb, m);
             store_node(dst, c, node_off(c, x, y), fa, tb);
         }
     }
@@ -277,6 +371,14 @@ __device__ __forceinline__ int wrap_index(int g, int n)
     return g >= n ? g % n : g;
 }
 
+// True when a tile, its ring and every node the ring pulls from lie strictly inside the
+// lattice: then no node of the tile or ring is a wall node and nothing wraps.
+template <int TY>
+__device__ __forceinline__ bool tile_interior(const LatticeConst& c, int X0, int Y0)
+{
+    return X0 >= 2 && X0 + (int)kBlock + 1 < c.nx && Y0 >= 2 && Y0 + TY + 1 < c.ny;
+}
+
 // Phase 1 for thread tid of the workgroup whose tile starts at (X0, Y0): node
 // (X0 - 1 + lx, Y0 - 1 + ly) of the tile with its ring, advanced from the stored buffer
 // into LDS. In a periodic direction a ring node outside the lattice is the wrapped
@@ -287,8 +389,19 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
 {
     typedef typename Wide<S>::type W;
     typedef Tile2<TY> T;
-    const int lane = tid % 64, wave = tid / 64;
+    const int lane = tid % 64;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
     constexpr int nwaves = NT / 64;
+    auto finish = [&](const float a[9], const float b[5], int lx, int ly) {
+        W fa[9], tb[5];
+        NodeMacro m;
+        collide<W, VH>(c, a, b, fa, tb, m);
+        S v[14];
+        round_node<S>(fa, tb, v);
+        const unsigned o = (unsigned)ly * T::XE + lx;
+#pragma unroll
+        for (int i = 0; i < 14; ++i) tile[i * T::P + o] = v[i];
+    };
     auto advance = [&](int lx, int ly) {
         int gx = X0 - 1 + lx, gy = Y0 - 1 + ly;
         if (gx < 0 || gx >= c.nx) {
@@ -300,20 +413,26 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
             gy = wrap_index(gy, c.ny);
         }
         float a[9], b[5];
-        W fa[9], tb[5];
-        NodeMacro m;
         gather_node<S, VH>(src, c, gx, gy, a, b);
-        collide<W, VH>(c, a, b, fa, tb, m);
-        S v[14];
-        round_node<S>(fa, tb, v);
-        const unsigned o = (unsigned)ly * T::XE + lx;
-#pragma unroll
-        for (int i = 0; i < 14; ++i) tile[i * T::P + o] = v[i];
+        finish(a, b, lx, ly);
     };
     // one wave per row for the kBlock interior columns, then the two ring columns
     static_assert(T::YE % nwaves == 0, "rows of the tile and ring per wave");
+    if (tile_interior<TY>(c, X0, Y0)) {
+        const ColBytes k = stored_cols<S>(X0 + lane);
+        const size_t rb = (size_t)c.rowlen * sizeof(S);
 #pragma unroll
-    for (int k = 0; k < T::YE / nwaves; ++k) advance(lane + 1, wave + k * nwaves);
+        for (int j = 0; j < T::YE / nwaves; ++j) {
+            const int ly = wave + j * nwaves;
+            const char* rc = stored_row(src, c.rowlen, Y0 - 1 + ly);
+            float a[9], b[5];
+            gather_interior<S, kBlock>(rc - rb, rc, rc + rb, k, a, b);
+            finish(a, b, lane + 1, ly);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < T::YE / nwaves; ++j) advance(lane + 1, wave + j * nwaves);
+    }
     for (int k = tid; k < 2 * T::YE; k += NT) advance(k < T::YE ? 0 : T::XE - 1, k % T::YE);
 }
 
@@ -323,14 +442,34 @@ __device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeC
                                              int X0, int Y0, int tid)
 {
     typedef typename Wide<S>::type W;
-    const int lane = tid % 64, wave = tid / 64;
+    typedef Tile2<TY> T;
+    const int lane = tid % 64;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
     constexpr int nwaves = NT / 64;
-    const TileMem<S, TY> mem{tile, X0 - 1, Y0 - 1};
     const int gx = X0 + lane;
-    if (gx < c.nx) {
+    if (tile_interior<TY>(c, X0, Y0)) {
+        // LDS column of the node is lane + 1, its row ly + 1 (the ring is row and column 0)
+        const unsigned e = (unsigned)sizeof(S), cb = (unsigned)(lane + 1) * e;
+        const ColBytes k{cb - e, cb, cb + e};
+        const unsigned own = stored_cols<S>(gx).c;
+        constexpr unsigned rb = T::XE * sizeof(S);
 #pragma unroll
-        for (int k = 0; k < (TY + nwaves - 1) / nwaves; ++k) {
-            const int ly = wave + k * nwaves, gy = Y0 + ly;
+        for (int j = 0; j < (TY + nwaves - 1) / nwaves; ++j) {
+            const int ly = wave + j * nwaves;
+            if (ly >= TY) break;
+            const char* rc = reinterpret_cast<const char*>(tile) + (unsigned)(ly + 1) * rb;
+            float a[9], b[5];
+            W fa[9], tb[5];
+            NodeMacro m;
+            gather_interior<S, T::P>(rc - rb, rc, rc + rb, k, a, b);
+            collide<W, VH>(c, a, b, fa, tb, m);
+            store_node_at(reinterpret_cast<S*>(stored_row(dst, c.rowlen, Y0 + ly) + own), fa, tb);
+        }
+    } else if (gx < c.nx) {
+        const TileMem<S, TY> mem{tile, X0 - 1, Y0 - 1};
+#pragma unroll
+        for (int j = 0; j < (TY + nwaves - 1) / nwaves; ++j) {
+            const int ly = wave + j * nwaves, gy = Y0 + ly;
             if (ly >= TY || gy >= c.ny) break;
             float a[9], b[5];
             W fa[9], tb[5];

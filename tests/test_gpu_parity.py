@@ -236,3 +236,60 @@ def test_determinism():
     assert da.mass == db.mass and da.sum_u2 == db.sum_u2 and list(da.dTdn) == list(db.dTdn)
     for x, y in zip(a.populations(), b.populations()):
         assert torch.equal(x, y)
+
+
+def _interior_case(kind):
+    """Lattices wide and tall enough that most two-step tiles (64 x 14 plus a ring) and
+    most one-step blocks lie strictly inside: they take the interior gather."""
+    nx, ny = (800, 40) if kind == "wide" else (300, 100)
+    rng = np.random.default_rng({"walls": 1, "periodic": 2, "viscous": 3, "wide": 4}[kind])
+    robin = [W.robin(1, 0.5, 0.05, 0.03), W.robin(0.5, 1, -0.05, -0.02), W.robin(1, 1, 0, 0.01),
+             W.dirichlet(0.0, u_wall=-0.04)]
+    if kind == "periodic":
+        prob = W.problem(nx, ny, 0.05, 0.05, [W.PERIODIC] * 4, Fx=2e-6, Fy=1e-6, Q=1e-5)
+    elif kind == "viscous":
+        prob = W.problem(nx, ny, 0.07, 0.05, [W.PERIODIC, W.PERIODIC] + robin[2:], Fx=3e-6, Q=1e-5,
+                         T0=0.05, viscous_heating=True)
+    else:
+        prob = W.problem(nx, ny, 0.07, 0.05, robin, g_beta=1e-4, Fx=3e-6, Q=1e-5, T0=0.05)
+    fields = {"ux": f32(0.02 * rng.uniform(-1, 1, (ny, nx))), "uy": f32(0.02 * rng.uniform(-1, 1, (ny, nx))),
+              "T": f32(prob["T0"] + 0.1 * rng.uniform(-1, 1, (ny, nx)))}
+    return prob, fields
+
+
+@pytest.mark.parametrize("kind", ["walls", "periodic", "viscous", "wide"])
+def test_interior_tiles(kind):
+    """Interior tiles and blocks skip the wall logic and address their sources through row
+    pointers: two-step launches and one-step launches of several shapes give the same state
+    bit for bit, and that state matches the oracle."""
+    import torch
+    prob, fields = _interior_case(kind)
+    steps = 41
+    runs = [run_gpu(prob, steps, fields, launch=dict(steps_per_launch=2))]
+    for bx, by, rows, remap in [(256, 1, 1, 0), (64, 4, 1, 1), (128, 2, 2, 0), (32, 2, 1, 0)]:
+        runs.append(run_gpu(prob, steps, fields, launch=dict(block_x=bx, block_y=by, rows_per_thread=rows,
+                                                               xcd_remap=remap, steps_per_launch=1)))
+    for r in runs[1:]:
+        for x, y in zip(runs[0].populations(), r.populations()):
+            assert torch.equal(x, y)
+    o = run_oracle(prob, steps, fields)
+    e = field_errors(o, runs[0])
+    report("interior %s (%dx%d)" % (kind, prob["nx"], prob["ny"]), e)
+    assert e["u"] <= TOL and e["T"] <= TOL and e["rho_abs"] <= 1e-6
+    p = population_errors(o, runs[0], prob["T0"])
+    assert p["f"] <= TOL and p["g"] <= TOL, p
+
+
+@pytest.mark.parametrize("kind", ["walls", "wide"])
+def test_interior_blocks_fp16(kind):
+    """FP16 storage: one-step launches of several shapes (interior and generic blocks mixed
+    differently) give the same state bit for bit."""
+    import torch
+    import paper_1801_04577_amd as clbm
+    prob, fields = _interior_case(kind)
+    runs = [run_gpu(prob, 23, fields, precision=clbm.CLBM_FP16_SHIFTED,
+                    launch=dict(block_x=bx, block_y=by, rows_per_thread=rows, xcd_remap=remap))
+            for bx, by, rows, remap in [(256, 1, 1, 0), (64, 4, 1, 1), (512, 1, 2, 0), (32, 2, 1, 0)]]
+    for r in runs[1:]:
+        for x, y in zip(runs[0].populations(), r.populations()):
+            assert torch.equal(x, y)
