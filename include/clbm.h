@@ -99,12 +99,13 @@ typedef struct {
  * steps_per_launch = 1: one time step per launch; block_x * block_y threads per
  * workgroup (multiple of 64, at most 1024), rows_per_thread in {1, 2, 4}, xcd_remap != 0
  * maps consecutive tiles to the same XCD.
- * steps_per_launch = 2 (FP32 storage only): two time steps per launch, the intermediate
- * state kept in LDS by workgroups of 512 threads that own 64 x 14 node tiles; xcd_remap
- * applies to these tiles too, the other fields shape only the single step that ends an
- * odd step count. Both modes give bitwise identical states.
- * A zeroed struct selects the built-in default (two steps per launch with xcd_remap for
- * FP32 storage, one step per launch for FP16). */
+ * steps_per_launch = 2: two time steps per launch, the intermediate state kept in LDS
+ * (rounded into the storage type exactly as a stored state) by workgroups of 512 threads
+ * that own tiles of 64 x 14 nodes;
+ * xcd_remap applies to these tiles too, the other fields shape only the single step that
+ * ends an odd step count (256 x 1 threads, one row each, if they do not form a valid
+ * shape). Both modes give bitwise identical states.
+ * A zeroed struct selects the built-in default: two steps per launch with xcd_remap. */
 typedef struct {
     int block_x, block_y, rows_per_thread, xcd_remap;
     int steps_per_launch;

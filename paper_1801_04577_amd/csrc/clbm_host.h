@@ -27,6 +27,9 @@ constexpr size_t kAlign = 256;   // workspace region alignment, bytes
 
 // Two steps per launch: tiles of kBlock x kTwoStepRows nodes, kTwoStepThreads threads.
 constexpr int kTwoStepRows = 14;
+// FP16 storage: same tile (half the LDS, so three workgroups fit a CU).
+constexpr int kTwoStepRowsF16 = 14;
+constexpr int kTwoStepThreadsF16 = 512;
 constexpr int kTwoStepThreads = 512;
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }

@@ -212,23 +212,33 @@ static StepLaunch plan_step(const LatticeConst& c, int precision, const clbm_lau
 
 static bool launch_ok(const clbm_launch& L, int precision)
 {
-    if (L.steps_per_launch == 2) return precision == CLBM_FP32;
+    if (L.steps_per_launch == 2) return precision == CLBM_FP32 || precision == CLBM_FP16_SHIFTED;
     if (L.steps_per_launch != 1) return false;
     const int threads = L.block_x * L.block_y;
     if (L.block_x < 1 || L.block_y < 1 || threads % 64 != 0 || threads > 1024) return false;
     return L.rows_per_thread == 1 || L.rows_per_thread == 2 || L.rows_per_thread == 4;
 }
 
-static clbm_launch default_launch(int precision)
+// The single-step shape used where none is given: 256 x 1 threads, one row each.
+static clbm_launch default_single_launch()
 {
     clbm_launch L;
     L.block_x = 256;
     L.block_y = 1;
     L.rows_per_thread = 1;
-    // FP32 storage: two steps per launch over XCD-ordered tiles (the single step that
-    // ends an odd count then also takes the remap, at no measurable cost)
-    L.xcd_remap = precision == CLBM_FP32 ? 1 : 0;
-    L.steps_per_launch = precision == CLBM_FP32 ? 2 : 1;
+    L.xcd_remap = 0;
+    L.steps_per_launch = 1;
+    return L;
+}
+
+static clbm_launch default_launch(int precision)
+{
+    clbm_launch L = default_single_launch();
+    // two steps per launch over XCD-ordered tiles (the single step that ends an odd
+    // count then also takes the remap, at no measurable cost)
+    L.xcd_remap = 1;
+    L.steps_per_launch = 2;
+    (void)precision;
     return L;
 }
 
@@ -238,18 +248,27 @@ struct Step2Launch {
     int tiles_x, tiles_total, remap;
 };
 
-static Step2Launch plan_step2(const LatticeConst& c, const clbm_launch& L)
+template <typename S, int TY, int NT>
+static const void* step2_fn(bool viscous)
+{
+    return viscous ? reinterpret_cast<const void*>(&k_step2<S, true, TY, NT>)
+                   : reinterpret_cast<const void*>(&k_step2<S, false, TY, NT>);
+}
+
+static Step2Launch plan_step2(const LatticeConst& c, int precision, const clbm_launch& L)
 {
     Step2Launch s;
-    s.fn = c.viscous ? reinterpret_cast<const void*>(&k_step2<float, true, kTwoStepRows, kTwoStepThreads>)
-                     : reinterpret_cast<const void*>(&k_step2<float, false, kTwoStepRows, kTwoStepThreads>);
+    const bool f16 = precision == CLBM_FP16_SHIFTED;
+    const int rows = f16 ? kTwoStepRowsF16 : kTwoStepRows;
+    s.fn = f16 ? step2_fn<__half, kTwoStepRowsF16, kTwoStepThreadsF16>(c.viscous != 0)
+               : step2_fn<float, kTwoStepRows, kTwoStepThreads>(c.viscous != 0);
     s.tiles_x = (c.nx + (int)kBlock - 1) / (int)kBlock;
-    const int tiles_y = (c.ny + kTwoStepRows - 1) / kTwoStepRows;
+    const int tiles_y = (c.ny + rows - 1) / rows;
     s.tiles_total = s.tiles_x * tiles_y;
     s.remap = L.xcd_remap ? 1 : 0;
     const int g = s.remap ? (int)align_up((size_t)s.tiles_total, 8) : s.tiles_total;
     s.grid = dim3((unsigned)g, 1, 1);
-    s.block = dim3(kTwoStepThreads, 1, 1);
+    s.block = dim3(f16 ? kTwoStepThreadsF16 : kTwoStepThreads, 1, 1);
     return s;
 }
 
@@ -328,7 +347,7 @@ clbm_status plan_steps(clbm_handle* h, int n, int from, Emit emit)
 {
     const bool two = h->launch.steps_per_launch == 2;
     const StepLaunch s1 = plan_step(h->c, h->p.precision, h->launch);
-    const Step2Launch s2 = plan_step2(h->c, h->launch);
+    const Step2Launch s2 = plan_step2(h->c, h->p.precision, h->launch);
     int cur = from;
     while (n > 0) {
         LaunchArgs a;
@@ -673,7 +692,7 @@ clbm_status clbm_set_launch(clbm_handle* h, const clbm_launch* launch)
         clbm_launch one = L;
         one.steps_per_launch = 1;
         if (!launch_ok(one, h->p.precision)) {
-            const clbm_launch d = default_launch(CLBM_FP16_SHIFTED);
+            const clbm_launch d = default_single_launch();
             L.block_x = d.block_x;
             L.block_y = d.block_y;
             L.rows_per_thread = d.rows_per_thread;

@@ -208,9 +208,31 @@ def test_two_step_launch_viscous_and_fp16_rules():
     for x, y in zip(a.populations(), b.populations()):
         assert torch.equal(x, y)
     s = clbm.Solver(W.channel(), clbm.CLBM_FP16_SHIFTED)
+    assert s.get_launch()["steps_per_launch"] == 2
+    s.set_launch(steps_per_launch=1)
     assert s.get_launch()["steps_per_launch"] == 1
     with pytest.raises(clbm.ClbmError):
-        s.set_launch(steps_per_launch=2)
+        s.set_launch(steps_per_launch=3)
+
+
+@pytest.mark.parametrize("case", ["seed0", "seed5", "seed11", "walls", "periodic", "viscous", "wide"])
+@pytest.mark.parametrize("steps", [2, 37])
+def test_two_step_launches_equal_single_steps_fp16(case, steps):
+    """FP16 storage, two steps per launch (64 x 14 tiles, the intermediate state rounded
+    into binary16 in LDS) against one step per launch: bitwise identical states, also
+    through replayed graphs of 6 steps."""
+    import torch
+    import paper_1801_04577_amd as clbm
+    prob, fields = random_case(int(case[4:])) if case.startswith("seed") else _interior_case(case)
+    h = clbm.CLBM_FP16_SHIFTED
+    a = run_gpu(prob, steps, fields, precision=h, launch=dict(block_x=256, steps_per_launch=1))
+    b = run_gpu(prob, steps, fields, precision=h, launch=dict(steps_per_launch=2))
+    c = run_gpu(prob, steps + 12, fields, precision=h, launch=dict(steps_per_launch=2), graph=6)
+    d = run_gpu(prob, steps + 12, fields, precision=h, launch=dict(block_x=256, steps_per_launch=1))
+    for x, y in zip(a.populations(), b.populations()):
+        assert torch.equal(x, y)
+    for x, y in zip(c.populations(), d.populations()):
+        assert torch.equal(x, y)
 
 
 def test_checkpoint_resume_bitwise():
