@@ -419,16 +419,19 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
     // one wave per row for the kBlock interior columns, then the two ring columns
     static_assert(T::YE % nwaves == 0, "rows of the tile and ring per wave");
     if (tile_interior<TY>(c, X0, Y0)) {
+        // all rows of the wave are loaded before the first is collided, so the later rows'
+        // loads are in flight during the earlier rows' arithmetic
+        constexpr int R = T::YE / nwaves;
         const ColBytes k = stored_cols<S>(X0 + lane);
         const size_t rb = (size_t)c.rowlen * sizeof(S);
+        float a[R][9], b[R][5];
 #pragma unroll
-        for (int j = 0; j < T::YE / nwaves; ++j) {
-            const int ly = wave + j * nwaves;
-            const char* rc = stored_row(src, c.rowlen, Y0 - 1 + ly);
-            float a[9], b[5];
-            gather_interior<S, kBlock>(rc - rb, rc, rc + rb, k, a, b);
-            finish(a, b, lane + 1, ly);
+        for (int j = 0; j < R; ++j) {
+            const char* rc = stored_row(src, c.rowlen, Y0 - 1 + wave + j * nwaves);
+            gather_interior<S, kBlock>(rc - rb, rc, rc + rb, k, a[j], b[j]);
         }
+#pragma unroll
+        for (int j = 0; j < R; ++j) finish(a[j], b[j], lane + 1, wave + j * nwaves);
     } else {
 #pragma unroll
         for (int j = 0; j < T::YE / nwaves; ++j) advance(lane + 1, wave + j * nwaves);
