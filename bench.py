@@ -548,6 +548,7 @@ def main():
     copy_gbs, copy_ms = copy_ceiling(torch, clbm)
     log("bench: reference copy %.0f GB/s" % copy_gbs)
 
+    traffic = measured_traffic(args.precision, args.n, spl)
     out = {
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 5),
@@ -561,7 +562,10 @@ def main():
                    "launch": s.get_launch()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.precision, args.n, spl),
+                     "traffic": traffic,
+                     # measured HBM bytes over the same launch time: how busy HBM really is
+                     # (below `achieved` when a launch advances two steps on one read)
+                     "traffic_rate_GBs": None if traffic is None else round(traffic / (kms * 1e-3) / 1e9, 1),
                      "algorithmic_bytes_per_launch": bpl * nodes * spl,
                      "kernel": "k_step2" if spl == 2 else "k_step", "steps_per_launch": spl,
                      "kernel_avg_ms": round(kms, 5), "bytes_per_lup": bpl,
