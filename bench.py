@@ -215,6 +215,86 @@ def summarize_profiles(trace_db, fetch_db, write_db, precision, n, command):
     print(json.dumps({"written": tag, "traffic_over_algorithmic": traffic / alg}))
 
 
+def small_configs(args):
+    """The cache-resident configurations on the GPU (their working sets fit the 256 MB
+    Infinity Cache, so they are launch-bound and get no HBM fraction; steps are replayed
+    from graphs of 100 steps), each next to the FP64 oracle timed on the host cores with
+    one thread and with all threads (bounded step counts, stated per entry)."""
+    import numpy as np
+    import torch
+    import paper_1801_04577_amd as clbm
+    import workloads as W
+    import oracle
+
+    def gpu_rate(prob, steps, precision=clbm.CLBM_FP32, T_init=None):
+        s = clbm.Solver(prob, precision)
+        s.set_graph(100)
+        s.init(T=None if T_init is None else torch.from_numpy(T_init))
+        s.step(200)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        d = s.diagnostics()
+        return {"steps": steps, "seconds": round(dt, 4),
+                "mlups": round(prob["nx"] * prob["ny"] * steps / dt / 1e6, 1), "nan": d.nan_count}
+
+    def oracle_rate(prob, steps, nthreads):
+        o = oracle.Sim(prob, nthreads=nthreads)
+        o.step(1)
+        t0 = time.perf_counter()
+        o.step(steps)
+        dt = time.perf_counter() - t0
+        return {"threads": nthreads, "steps": steps, "seconds": round(dt, 3),
+                "mlups": round(prob["nx"] * prob["ny"] * steps / dt / 1e6, 3)}
+
+    nth = oracle.default_threads()
+    out = []
+    c0 = W.channel()
+    log("configs: channel 64x32")
+    out.append({"config": "channel 64x32 (periodic x, walls in y, g_x 1e-6, nu 0.05, Pr 0.71, Q 1e-4)",
+                "gpu_fp32": gpu_rate(c0, 10000),
+                "cpu_baseline": [dict(oracle_rate(c0, 10000, 1), kind="oracle"),
+                                 dict(oracle_rate(c0, 10000, nth), kind="oracle")]})
+    c1 = W.cavity(256, Ra=1e5, Pr=0.71)
+    T1 = W.cavity_initial_T(c1, seed=12345).astype(np.float32)
+    log("configs: cavity 256^2 to residual 1e-7")
+    s = clbm.Solver(c1)
+    s.set_graph(100)
+    s.init(T=torch.from_numpy(T1))
+    s.diagnostics()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while s.t < 3_000_000:
+        s.step(1000)
+        d = s.diagnostics()
+        if d.nan_count or max(d.res_u, d.res_T) < 1e-7:
+            break
+    dt = time.perf_counter() - t0
+    H, dT = 256, 1.0
+    c1_run = {"steps_to_residual_1e-7": int(s.t), "seconds": round(dt, 3),
+              "mlups": round(256 * 256 * s.t / dt / 1e6, 1), "res_u": d.res_u, "res_T": d.res_T,
+              "Nu_cold_wall": round(clbm.nusselt(d, 1, H, dT, into_wall=True), 5),
+              "Nu_hot_wall": round(clbm.nusselt(d, 0, H, dT, into_wall=False), 5),
+              "Nu_cold_wall_link_flux": round(clbm.nusselt_flux(d, 1, H, dT, c1["alpha"], into_wall=True), 5),
+              "nan": d.nan_count}
+    out.append({"config": "cavity 256^2 Ra 1e5 Pr 0.71, walls +-0.5, seeded noise 1e-4, run to residual 1e-7 "
+                          "(diagnostics every 1000 steps)",
+                "gpu_fp32": c1_run,
+                "cpu_baseline": [dict(oracle_rate(c1, 300, 1), kind="oracle"),
+                                 dict(oracle_rate(c1, 1000, nth), kind="oracle")]})
+    c2 = W.cavity(512, Ra=1e6, Pr=0.71, Q=5e-6)
+    T2 = W.cavity_initial_T(c2, seed=12345).astype(np.float32)
+    log("configs: cavity 512^2 stand-in")
+    out.append({"config": "cavity 512^2 Ra 1e6 Pr 0.71 Q 5e-6 (stand-in of the 4096^2 cavity)",
+                "gpu_fp32": gpu_rate(c2, 20000, T_init=T2),
+                "gpu_fp16s": gpu_rate(c2, 20000, clbm.CLBM_FP16_SHIFTED, T_init=T2),
+                "cpu_baseline": [dict(oracle_rate(c2, 100, 1), kind="oracle"),
+                                 dict(oracle_rate(c2, 200, nth), kind="oracle")]})
+    return out
+
+
 def batched_sweep(args):
     """The batched form on the 256-cavity sweep: autotuned one-launch-per-step over a
     device tile list, against a loop of per-cavity launches of the single-lattice step on
@@ -479,6 +559,8 @@ def main():
     ap.add_argument("--launch", default="", help="block_x,block_y,rows,remap[,steps_per_launch]")
     ap.add_argument("--kernel-launches", type=int, default=200)
     ap.add_argument("--batched", action="store_true", help="run the batched-sweep benchmark only")
+    ap.add_argument("--configs", action="store_true",
+                    help="the cache-resident configurations (64x32 channel, 256^2 to residual, 512^2) and the oracle")
     ap.add_argument("--sweep-count", type=int, default=256)
     ap.add_argument("--sweep-steps", type=int, default=200)
     ap.add_argument("--sweep-max-steps", type=int, default=200000)
@@ -515,6 +597,9 @@ def main():
     torch.cuda.set_device(0)
     if args.batched:
         print(json.dumps({"metric": METRIC, "batched": batched_sweep(args)}), flush=True)
+        return
+    if args.configs:
+        print(json.dumps({"metric": METRIC, "configs": small_configs(args)}), flush=True)
         return
     if args.warmstart:
         r = warmstart_experiment(args)
