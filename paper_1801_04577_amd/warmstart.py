@@ -6,7 +6,7 @@ and clbm_net_features) to its steady fields on a fixed grid, in the problem's ow
 u/U, v/U with U = sqrt(g beta dT H), and (T - T0)/dT. The prediction is resampled onto
 the lattice (clbm_resample_bilinear) and becomes the initial state of the solver
 (clbm_batch_init, equilibrium at the predicted u and T). The cold start, T = T0 plus a
-seeded perturbation, is the fallback and the judge: both runs go to the same residual
+seeded perturbation, is the fallback and the reference: both runs go to the same residual
 and their Nusselt numbers are compared.
 
 This module orchestrates library calls; every array operation of the method runs in
