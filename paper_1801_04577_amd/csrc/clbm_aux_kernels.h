@@ -29,7 +29,7 @@ __global__ void __launch_bounds__(256) k_init(S* __restrict__ dst, const Lattice
     NodeMacro m;
     if (c.viscous) collide<typename Wide<S>::type, true>(c, a, b, fa, tb, m);
     else collide(c, a, b, fa, tb, m);
-    store_node(dst, c, node_off(c, x, y), fa, tb);
+    store_node(dst, c, x, y, fa, tb);
 }
 
 template <typename S>

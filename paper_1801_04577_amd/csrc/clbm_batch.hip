@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(1024) k_batch_step(const BatchInst* __restrict
                 gather_node(src, c, x, y, a, b);
                 collide(c, a, b, fa, tb, m);
             }
-            store_node(dst, c, node_off(c, x, y), fa, tb);
+            store_node(dst, c, x, y, fa, tb);
         }
     }
 }

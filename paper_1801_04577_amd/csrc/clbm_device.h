@@ -88,10 +88,10 @@ template <> __device__ __forceinline__ float ld<__half>(const __half* p) { retur
 
 // Unbiased rounding into storage. x lies between the nearest storable value f and its
 // neighbour g on the other side of x; g is taken with probability |x - f|/|g - f|. The
-// uniform variates come from a hash of the bits of the node's results (store_node), so
-// the expected stored value is x and the decision is a deterministic function of the
-// results: runs are reproducible, and a state that no longer changes is stored
-// identically every step.
+// uniform variates come from a hash of the node's coordinates and the bits of its
+// results (round_node), so the expected stored value is x and the decision is a
+// deterministic function of the node and its results: runs are reproducible, and a
+// state that no longer changes is stored identically every step.
 __device__ __forceinline__ unsigned mix32(unsigned h)
 {
     h ^= h >> 16;

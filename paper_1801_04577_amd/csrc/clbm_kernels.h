@@ -175,16 +175,19 @@ __device__ __forceinline__ void gather_node(const S* __restrict__ src, const Lat
     gather_mem<VH>(global_mem(src, c), c, x, y, a, b);
 }
 
-// Round the post-collision state of one node into the storage type: the deviations,
-// computed wider than the storage, go through the unbiased rounding of sr_round. One
-// hash per node mixes the sum of the bits of all 14 results (equal results do not
-// cancel in a sum); the k-th value takes h + k * 0x9E3779B9 (a Weyl sequence), each
-// uniform on its own.
+// Round the post-collision state of one node (x, y) into the storage type: the
+// deviations, computed wider than the storage, go through the unbiased rounding of
+// sr_round. One hash per node mixes the node's coordinates with the sum of the bits of
+// all 14 results (equal results do not cancel in a sum); the k-th value takes
+// h + k * 0x9E3779B9 (a Weyl sequence), each uniform on its own. The coordinates give
+// nodes in equal states independent variates: a uniform lattice whose increments are far
+// below a unit in the last place would otherwise round every node alike and could keep
+// rounding to the same state. A state that no longer changes is still stored identically.
 template <typename S>
 __device__ __forceinline__ void round_node(const typename Wide<S>::type fa[9],
-                                           const typename Wide<S>::type tb[5], S out[14])
+                                           const typename Wide<S>::type tb[5], S out[14], int x, int y)
 {
-    unsigned acc = 0;
+    unsigned acc = (unsigned)x * 0x9E3779B1u + (unsigned)y * 0x632BE5ABu;
 #pragma unroll
     for (int i = 0; i < 9; ++i) acc += hash_bits(fa[i]);
 #pragma unroll
@@ -196,25 +199,26 @@ __device__ __forceinline__ void round_node(const typename Wide<S>::type fa[9],
     for (int i = 0; i < 5; ++i) out[9 + i] = sr_round(tb[i], h + (unsigned)(9 + i) * 0x9E3779B9u);
 }
 
-// Store the post-collision state of one node (own = node_off), nontemporal.
+// Store the post-collision state of node (x, y), nontemporal.
 template <typename S>
-__device__ __forceinline__ void store_node(S* __restrict__ dst, const LatticeConst& c, unsigned own,
+__device__ __forceinline__ void store_node(S* __restrict__ dst, const LatticeConst& c, int x, int y,
                                            const typename Wide<S>::type fa[9],
                                            const typename Wide<S>::type tb[5])
 {
     S v[14];
-    round_node<S>(fa, tb, v);
+    round_node<S>(fa, tb, v, x, y);
+    const unsigned own = node_off(c, x, y);
 #pragma unroll
     for (int i = 0; i < 14; ++i) st_nt(dst + i * kBlock + own, v[i]);
 }
 
-// Store the post-collision state of one node given the address of its population 0.
+// Store the post-collision state of node (x, y) given the address of its population 0.
 template <typename S>
 __device__ __forceinline__ void store_node_at(S* __restrict__ p0, const typename Wide<S>::type fa[9],
-                                              const typename Wide<S>::type tb[5])
+                                              const typename Wide<S>::type tb[5], int x, int y)
 {
     S v[14];
-    round_node<S>(fa, tb, v);
+    round_node<S>(fa, tb, v, x, y);
 #pragma unroll
     for (int i = 0; i < 14; ++i) st_nt(p0 + i * kBlock, v[i]);
 }
@@ -319,7 +323,7 @@ __global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __r
             NodeMacro m;
             gather_interior<S, kBlock>(rc - rb, rc, rc + rb, k, a, b);
             collide<W, VH>(c, a, b, fa, tb, m);
-            store_node_at(reinterpret_cast<S*>(stored_row(dst, c.rowlen, yw + r) + k.c), fa, tb);
+            store_node_at(reinterpret_cast<S*>(stored_row(dst, c.rowlen, yw + r) + k.c), fa, tb, x, yw + r);
         }
         return;
     }
@@ -333,7 +337,7 @@ __global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __r
             gather_node<S, VH>(src, c, x, y, a, b);
             NodeMacro m;
             collide<W, VH>(c, a, b, fa, tb, m);
-            store_node(dst, c, node_off(c, x, y), fa, tb);
+            store_node(dst, c, x, y, fa, tb);
         }
     }
 }
@@ -392,12 +396,12 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
     const int lane = tid % 64;
     const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
     constexpr int nwaves = NT / 64;
-    auto finish = [&](const float a[9], const float b[5], int lx, int ly) {
+    auto finish = [&](const float a[9], const float b[5], int gx, int gy, int lx, int ly) {
         W fa[9], tb[5];
         NodeMacro m;
         collide<W, VH>(c, a, b, fa, tb, m);
         S v[14];
-        round_node<S>(fa, tb, v);
+        round_node<S>(fa, tb, v, gx, gy);
         const unsigned o = (unsigned)ly * T::XE + lx;
 #pragma unroll
         for (int i = 0; i < 14; ++i) tile[i * T::P + o] = v[i];
@@ -414,7 +418,7 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
         }
         float a[9], b[5];
         gather_node<S, VH>(src, c, gx, gy, a, b);
-        finish(a, b, lx, ly);
+        finish(a, b, gx, gy, lx, ly);
     };
     // one wave per row for the kBlock interior columns, then the two ring columns
     static_assert(T::YE % nwaves == 0, "rows of the tile and ring per wave");
@@ -431,7 +435,8 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
             gather_interior<S, kBlock>(rc - rb, rc, rc + rb, k, a[j], b[j]);
         }
 #pragma unroll
-        for (int j = 0; j < R; ++j) finish(a[j], b[j], lane + 1, wave + j * nwaves);
+        for (int j = 0; j < R; ++j)
+            finish(a[j], b[j], X0 + lane, Y0 - 1 + wave + j * nwaves, lane + 1, wave + j * nwaves);
     } else {
 #pragma unroll
         for (int j = 0; j < T::YE / nwaves; ++j) advance(lane + 1, wave + j * nwaves);
@@ -466,7 +471,7 @@ __device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeC
             NodeMacro m;
             gather_interior<S, T::P>(rc - rb, rc, rc + rb, k, a, b);
             collide<W, VH>(c, a, b, fa, tb, m);
-            store_node_at(reinterpret_cast<S*>(stored_row(dst, c.rowlen, Y0 + ly) + own), fa, tb);
+            store_node_at(reinterpret_cast<S*>(stored_row(dst, c.rowlen, Y0 + ly) + own), fa, tb, gx, Y0 + ly);
         }
     } else if (gx < c.nx) {
         const TileMem<S, TY> mem{tile, X0 - 1, Y0 - 1};
@@ -479,7 +484,7 @@ __device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeC
             NodeMacro m;
             gather_mem<VH>(mem, c, gx, gy, a, b);
             collide<W, VH>(c, a, b, fa, tb, m);
-            store_node(dst, c, node_off(c, gx, gy), fa, tb);
+            store_node(dst, c, gx, gy, fa, tb);
         }
     }
 }
