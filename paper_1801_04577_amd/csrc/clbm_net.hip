@@ -132,49 +132,130 @@ __global__ void __launch_bounds__(256) k_conv(const bf16* __restrict__ x, int xC
 }
 
 // Weight gradient of one 3x3 convolution over a range of pixels (split-K):
-// part[s][co][tap][ci] = sum over pixels p of the split of dz[p][co] * x[src(p,tap)][ci].
-// One wave per (16 co x 16 ci) tile and tap; MFMA A = dz^T (co x pixels), B = shifted x
-// (pixels x ci); operands gathered element-wise (the reduction runs over pixels,
-// which are strided in NHWC).
-__global__ void __launch_bounds__(64) k_wgrad(const bf16* __restrict__ dz, int zC, int Cout,
-                                              const bf16* __restrict__ x, int xC, int xoff, int Cin,
-                                              int H, int W, int P, int pix_per_split,
-                                              float* __restrict__ part)
+// part[s][co][tap][ci] = sum over the pixels p of split s of dz[p][co] * x[src(p,tap)][ci],
+// a GEMM whose reduction runs over pixels, the slow index of NHWC. A workgroup of three
+// waves owns a 64 (co) x 64 (ci) block and one split; wave w takes the three taps of
+// kernel row w. Per chunk of 32 pixels the workgroup stages dz and the nine shifted input
+// tiles in LDS channel-major (the 32 pixels of one channel contiguous, two pixels per
+// 32-bit write), so every MFMA operand - 8 consecutive pixels of one channel - is one
+// 16-byte LDS read: A = dz^T (co x pixels), B = shifted x (pixels x ci). Each wave
+// reads its 4 dz fragments once per chunk and issues 48 MFMAs.
+constexpr int kWgP = 32;          // pixels per chunk: the MFMA K
+constexpr int kWgLd = kWgP + 8;   // LDS row stride in elements (staggers the banks)
+constexpr int kWgThreads = 192;
+
+__device__ __forceinline__ unsigned bf16_bits(bf16 v) { return (unsigned)__builtin_bit_cast(unsigned short, v); }
+
+__global__ void __launch_bounds__(kWgThreads) k_wgrad(const bf16* __restrict__ dz, int zC, int Cout,
+                                                      const bf16* __restrict__ x, int xC, int xoff, int Cin,
+                                                      int H, int W, int P, int pix_per_split,
+                                                      float* __restrict__ part)
 {
-    const int lane = threadIdx.x;
-    const int tiles_ci = Cin / 16;
-    const int co0 = (blockIdx.x / tiles_ci) * 16, ci0 = (blockIdx.x % tiles_ci) * 16;
-    const int tap = blockIdx.y, split = blockIdx.z;
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    __shared__ __attribute__((aligned(16))) bf16 sdz[64 * kWgLd];
+    __shared__ __attribute__((aligned(16))) bf16 sx[9][64 * kWgLd];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int cib_n = (Cin + 63) / 64;
+    const int co0 = (blockIdx.x / cib_n) * 64, ci0 = (blockIdx.x % cib_n) * 64;
+    const int split = blockIdx.y;
     const int HW = H * W;
     const int pbeg = split * pix_per_split, pend = min(P, pbeg + pix_per_split);
-    const int co = co0 + (lane & 15), ci = ci0 + (lane & 15), kq = (lane >> 4) * 8;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int pk = pbeg; pk < pend; pk += kKChunk) {
-        bf16x8 a, bv;
+    const int r16 = lane & 15, k8 = (lane >> 4) * 8;
+    // 16-row blocks of co and ci that exist (the rest of the 64 x 64 block is padding)
+    const int ncob = min(4, (Cout - co0 + 15) / 16), ncib = min(4, (Cin - ci0 + 15) / 16);
+    f32x4 acc[3][4][4];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int p = pk + kq + j;
-            float av = 0.f, xv = 0.f;
-            if (p < pend) {
-                av = bf2f(dz[(size_t)p * zC + co]);
-                const int b = p / HW, rem = p - b * HW, py = rem / W, px = rem - py * W;
-                const int sy = py + dy, sx = px + dx;
-                if (sy >= 0 && sy < H && sx >= 0 && sx < W)
-                    xv = bf2f(x[(size_t)(b * HW + sy * W + sx) * xC + xoff + ci]);
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[d][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero = {};
+    for (int pk = pbeg; pk < pend; pk += kWgP) {
+        // stage dz: 16 pixel pairs x 8 channel octets
+        if (tid < 128) {
+            const int pair = tid >> 3, oct = tid & 7;
+            const int p = pk + 2 * pair, co = co0 + 8 * oct;
+            bf16x8 v0 = zero, v1 = zero;
+            if (co < Cout) {
+                if (p < pend) v0 = *reinterpret_cast<const bf16x8*>(dz + (size_t)p * zC + co);
+                if (p + 1 < pend) v1 = *reinterpret_cast<const bf16x8*>(dz + (size_t)(p + 1) * zC + co);
             }
-            a[j] = f2bf(av);
-            bv[j] = f2bf(xv);
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                *reinterpret_cast<unsigned*>(&sdz[(8 * oct + c) * kWgLd + 2 * pair]) =
+                    bf16_bits(v0[c]) | (bf16_bits(v1[c]) << 16);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc, 0, 0, 0);
+        // stage the nine shifted input tiles: 9 taps x 16 pixel pairs x 8 channel octets
+        for (int t = tid; t < 9 * 128; t += kWgThreads) {
+            const int tap = t >> 7, pair = (t >> 3) & 15, oct = t & 7;
+            const int ci = ci0 + 8 * oct;
+            bf16x8 v[2] = {zero, zero};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int p = pk + 2 * pair + h;
+                if (p < pend && ci < Cin) {
+                    const int b = p / HW, rem = p - b * HW, py = rem / W, px = rem - py * W;
+                    const int sy = py + tap / 3 - 1, sx2 = px + tap % 3 - 1;
+                    if (sy >= 0 && sy < H && sx2 >= 0 && sx2 < W)
+                        v[h] = *reinterpret_cast<const bf16x8*>(x + (size_t)(b * HW + sy * W + sx2) * xC + xoff + ci);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                *reinterpret_cast<unsigned*>(&sx[tap][(8 * oct + c) * kWgLd + 2 * pair]) =
+                    bf16_bits(v[0][c]) | (bf16_bits(v[1][c]) << 16);
+        }
+        __syncthreads();
+        bf16x8 a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (i < ncob) a[i] = *reinterpret_cast<const bf16x8*>(&sdz[(16 * i + r16) * kWgLd + k8]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const bf16* xt = sx[3 * wave + d];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (j >= ncib) break;
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&xt[(16 * j + r16) * kWgLd + k8]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (i < ncob) acc[d][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bv, acc[d][i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // the next chunk overwrites the tiles
     }
     float* out = part + (size_t)split * Cout * 9 * Cin;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int r = co0 + 4 * (lane >> 4) + v;   // row of the result = output channel
-        out[((size_t)r * 9 + tap) * Cin + ci] = acc[v];
+    for (int d = 0; d < 3; ++d) {
+        const int tap = 3 * wave + d;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (i >= ncob || j >= ncib) continue;
+                const int ci = ci0 + 16 * j + r16;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int co = co0 + 16 * i + 4 * (lane >> 4) + v;   // row of the result
+                    out[((size_t)co * 9 + tap) * Cin + ci] = acc[d][i][j][v];
+                }
+            }
     }
 }
+
+// Pixels per split of the weight gradient of a layer with P pixels and the given padded
+// channel counts: about 768 workgroups, at least 8 chunks each.
+inline int wgrad_pixels_per_split(size_t P, int cout16, int cin_pad)
+{
+    const size_t blocks = (size_t)((cout16 + 63) / 64) * ((cin_pad + 63) / 64);
+    size_t splits = std::max<size_t>(1, 768 / blocks);
+    splits = std::min(splits, std::max<size_t>(1, P / (8 * kWgP)));
+    const size_t pps = (P + splits - 1) / splits;
+    return (int)((pps + kWgP - 1) / kWgP * kWgP);
+}
+
+// Pixels per split of the bias gradient.
+constexpr int kBiasPixelsPerSplit = 256;
 
 // Sum of the split partials in split order, written in the canonical layout
 // grad[co][ci][ky][kx] for co < Cout_real, ci < Cin_real (the partials use the padded
@@ -598,17 +679,19 @@ void layout_net(clbm_net* n, Alloc& a)
     n->grads = a.take<float>(off);
     n->adam_m = a.take<float>(off);
     n->adam_v = a.take<float>(off);
-    // split-K partials: pixels per split fixed at 4096
-    size_t wp = 0;
+    // split-K partials of the weight and bias gradients
+    size_t wp = 0, bp = 0;
     for (int k = 0; k < kLayers; ++k) {
         const Layer& l = n->L[k];
         const size_t P = (size_t)B * l.H * l.W;
-        const size_t splits = (P + 4095) / 4096;
-        wp = std::max(wp, splits * round_up(l.cout, 16) * 9 * l.cin_pad);
+        const int c16 = round_up(l.cout, 16);
+        const size_t pps = (size_t)wgrad_pixels_per_split(P, c16, l.cin_pad);
+        wp = std::max(wp, (P + pps - 1) / pps * c16 * 9 * l.cin_pad);
+        bp = std::max(bp, (P + kBiasPixelsPerSplit - 1) / kBiasPixelsPerSplit * l.cout);
     }
     n->wpart_floats = wp;
     n->wpart = a.take<float>(wp);
-    n->bpart = a.take<float>((P1 + 4095) / 4096 * std::max({w1, w2, w3, w4, d.cout}));
+    n->bpart = a.take<float>(bp);
     n->lpart = a.take<double>((P1 * 32 + 255) / 256);
     n->loss = a.take<double>(1);
 
@@ -713,22 +796,23 @@ clbm_status conv_backward(clbm_net* n, int k, TView dz)
     const Layer& l = n->L[k];
     const int B = n->d.batch;
     const int P = B * l.H * l.W;
-    const int pps = 4096;
-    const int splits = (P + pps - 1) / pps;
     const int cout16 = round_up(l.cout, 16);
+    const int pps = wgrad_pixels_per_split((size_t)P, cout16, l.cin_pad);
+    const int splits = (P + pps - 1) / pps;
     // weight gradient
-    hipLaunchKernelGGL(k_wgrad, dim3((cout16 / 16) * (l.cin_pad / 16), 9, splits), dim3(64), 0,
-                       n->stream, dz.p, dz.C, cout16, l.in.p, l.in.C, l.in.off, l.cin_pad, l.H, l.W,
+    hipLaunchKernelGGL(k_wgrad, dim3(((cout16 + 63) / 64) * ((l.cin_pad + 63) / 64), splits), dim3(kWgThreads),
+                       0, n->stream, dz.p, dz.C, cout16, l.in.p, l.in.C, l.in.off, l.cin_pad, l.H, l.W,
                        P, pps, n->wpart);
     CLBM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_wgrad_reduce, grid1((size_t)l.cout * 9 * l.cin), dim3(256), 0, n->stream,
                        n->wpart, splits, cout16, l.cin_pad, l.cout, l.cin, n->grads + l.woff);
     CLBM_HIP(hipGetLastError());
     // bias gradient
-    hipLaunchKernelGGL(k_bias_grad, dim3((l.cout + 63) / 64, splits), dim3(64, 4), 0, n->stream, dz.p,
-                       dz.C, l.cout, P, pps, n->bpart);
+    const int bsplits = (P + kBiasPixelsPerSplit - 1) / kBiasPixelsPerSplit;
+    hipLaunchKernelGGL(k_bias_grad, dim3((l.cout + 63) / 64, bsplits), dim3(64, 4), 0, n->stream, dz.p,
+                       dz.C, l.cout, P, kBiasPixelsPerSplit, n->bpart);
     CLBM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_bias_reduce, grid1(l.cout), dim3(256), 0, n->stream, n->bpart, splits, l.cout,
+    hipLaunchKernelGGL(k_bias_reduce, grid1(l.cout), dim3(256), 0, n->stream, n->bpart, bsplits, l.cout,
                        n->grads + l.boff);
     CLBM_HIP(hipGetLastError());
     // input gradient: convolution of dz with the flipped, transposed kernel
