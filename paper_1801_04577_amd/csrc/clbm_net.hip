@@ -244,11 +244,12 @@ __global__ void __launch_bounds__(kWgThreads) k_wgrad(const bf16* __restrict__ d
 }
 
 // Pixels per split of the weight gradient of a layer with P pixels and the given padded
-// channel counts: about 768 workgroups, at least 8 chunks each.
+// channel counts: about 512 workgroups (two per CU), at most 256 splits, at least 8
+// chunks each.
 inline int wgrad_pixels_per_split(size_t P, int cout16, int cin_pad)
 {
     const size_t blocks = (size_t)((cout16 + 63) / 64) * ((cin_pad + 63) / 64);
-    size_t splits = std::max<size_t>(1, 768 / blocks);
+    size_t splits = std::min<size_t>(256, std::max<size_t>(1, 512 / blocks));
     splits = std::min(splits, std::max<size_t>(1, P / (8 * kWgP)));
     const size_t pps = (P + splits - 1) / splits;
     return (int)((pps + kWgP - 1) / kWgP * kWgP);
@@ -259,18 +260,21 @@ constexpr int kBiasPixelsPerSplit = 256;
 
 // Sum of the split partials in split order, written in the canonical layout
 // grad[co][ci][ky][kx] for co < Cout_real, ci < Cin_real (the partials use the padded
-// strides Cout, Cin).
+// strides Cout, Cin). Threads run along the partials' own layout [co][tap][ci], so
+// the reads of each split are contiguous across a wave.
 __global__ void k_wgrad_reduce(const float* __restrict__ part, int splits, int Cout, int Cin,
                                int Cout_real, int Cin_real, float* __restrict__ grad)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int total = Cout_real * 9 * Cin_real;
-    if (k >= total) return;
-    const int co = k / (9 * Cin_real), r = k - co * 9 * Cin_real;
-    const int ci = r / 9, tap = r - ci * 9;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t plane = (size_t)Cout * 9 * Cin;
+    if (k >= plane) return;
+    const int co = (int)(k / (9 * (size_t)Cin)), r = (int)(k - (size_t)co * 9 * Cin);
+    const int tap = r / Cin, ci = r - tap * Cin;
+    if (co >= Cout_real || ci >= Cin_real) return;
     float s = 0.f;
-    for (int sp = 0; sp < splits; ++sp) s += part[(((size_t)sp * Cout + co) * 9 + tap) * Cin + ci];
-    grad[k] = s;
+#pragma unroll 8
+    for (int sp = 0; sp < splits; ++sp) s += part[sp * plane + k];
+    grad[((size_t)co * Cin_real + ci) * 9 + tap] = s;
 }
 
 // Bias gradient: db[c] = sum over pixels of dz[p][c]; block (64 channels x 4 rows),
@@ -292,13 +296,22 @@ __global__ void __launch_bounds__(256) k_bias_grad(const bf16* __restrict__ dz, 
                                       (lds[2][threadIdx.x] + lds[3][threadIdx.x]);
 }
 
-__global__ void k_bias_reduce(const float* __restrict__ part, int splits, int C, float* __restrict__ g)
+// Sum of the bias partials of channel blockIdx.x: each thread sums a fixed strided
+// subset of the splits, then a fixed-order tree over the 256 threads.
+__global__ void __launch_bounds__(256) k_bias_reduce(const float* __restrict__ part, int splits, int C,
+                                                     float* __restrict__ g)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
+    __shared__ float lds[256];
+    const int c = blockIdx.x, t = threadIdx.x;
     float s = 0.f;
-    for (int sp = 0; sp < splits; ++sp) s += part[(size_t)sp * C + c];
-    g[c] = s;
+    for (int sp = t; sp < splits; sp += 256) s += part[(size_t)sp * C + c];
+    lds[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) lds[t] += lds[t + w];
+        __syncthreads();
+    }
+    if (t == 0) g[c] = lds[0];
 }
 
 // Canonical FP32 weights -> BF16 forward layout wf[n][tap][ci] (n < Npad, ci < CinPad,
@@ -804,7 +817,7 @@ clbm_status conv_backward(clbm_net* n, int k, TView dz)
                        0, n->stream, dz.p, dz.C, cout16, l.in.p, l.in.C, l.in.off, l.cin_pad, l.H, l.W,
                        P, pps, n->wpart);
     CLBM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_wgrad_reduce, grid1((size_t)l.cout * 9 * l.cin), dim3(256), 0, n->stream,
+    hipLaunchKernelGGL(k_wgrad_reduce, grid1((size_t)cout16 * 9 * l.cin_pad), dim3(256), 0, n->stream,
                        n->wpart, splits, cout16, l.cin_pad, l.cout, l.cin, n->grads + l.woff);
     CLBM_HIP(hipGetLastError());
     // bias gradient
@@ -812,7 +825,7 @@ clbm_status conv_backward(clbm_net* n, int k, TView dz)
     hipLaunchKernelGGL(k_bias_grad, dim3((l.cout + 63) / 64, bsplits), dim3(64, 4), 0, n->stream, dz.p,
                        dz.C, l.cout, P, kBiasPixelsPerSplit, n->bpart);
     CLBM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_bias_reduce, grid1(l.cout), dim3(256), 0, n->stream, n->bpart, bsplits, l.cout,
+    hipLaunchKernelGGL(k_bias_reduce, dim3(l.cout), dim3(256), 0, n->stream, n->bpart, bsplits, l.cout,
                        n->grads + l.boff);
     CLBM_HIP(hipGetLastError());
     // input gradient: convolution of dz with the flipped, transposed kernel
