@@ -134,66 +134,67 @@ __global__ void __launch_bounds__(256) k_conv(const bf16* __restrict__ x, int xC
 // Weight gradient of one 3x3 convolution over a range of pixels (split-K):
 // part[s][co][tap][ci] = sum over the pixels p of split s of dz[p][co] * x[src(p,tap)][ci],
 // a GEMM whose reduction runs over pixels, the slow index of NHWC. A workgroup of three
-// waves owns a 64 (co) x 64 (ci) block and one split; wave w takes the three taps of
-// kernel row w. Per chunk of 32 pixels the workgroup stages dz and the nine shifted input
-// tiles in LDS channel-major (the 32 pixels of one channel contiguous, two pixels per
-// 32-bit write), so every MFMA operand - 8 consecutive pixels of one channel - is one
-// 16-byte LDS read: A = dz^T (co x pixels), B = shifted x (pixels x ci). Each wave
-// reads its 4 dz fragments once per chunk and issues 48 MFMAs.
+// waves owns a (16 NCO) co x (16 NCI) ci block and one split; wave w takes the three
+// taps of kernel row w. Per chunk of 32 pixels the workgroup stages dz and the nine
+// shifted input tiles in LDS channel-major (the 32 pixels of one channel contiguous, two
+// pixels per 32-bit write), so every MFMA operand - 8 consecutive pixels of one channel -
+// is one 16-byte LDS read: A = dz^T (co x pixels), B = shifted x (pixels x ci). Each wave
+// reads its NCO dz fragments once per chunk and issues 3 NCO NCI MFMAs. NCO and NCI
+// divide the padded channel counts (16-channel blocks), so the block has no padding.
 constexpr int kWgP = 32;          // pixels per chunk: the MFMA K
 constexpr int kWgLd = kWgP + 8;   // LDS row stride in elements (staggers the banks)
 constexpr int kWgThreads = 192;
 
 __device__ __forceinline__ unsigned bf16_bits(bf16 v) { return (unsigned)__builtin_bit_cast(unsigned short, v); }
 
+template <int NCO, int NCI>
 __global__ void __launch_bounds__(kWgThreads) k_wgrad(const bf16* __restrict__ dz, int zC, int Cout,
                                                       const bf16* __restrict__ x, int xC, int xoff, int Cin,
                                                       int H, int W, int P, int pix_per_split,
                                                       float* __restrict__ part)
 {
-    __shared__ __attribute__((aligned(16))) bf16 sdz[64 * kWgLd];
-    __shared__ __attribute__((aligned(16))) bf16 sx[9][64 * kWgLd];
+    constexpr int CO = 16 * NCO, CI = 16 * NCI;
+    __shared__ __attribute__((aligned(16))) bf16 sdz[CO * kWgLd];
+    __shared__ __attribute__((aligned(16))) bf16 sx[9][CI * kWgLd];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int cib_n = (Cin + 63) / 64;
-    const int co0 = (blockIdx.x / cib_n) * 64, ci0 = (blockIdx.x % cib_n) * 64;
+    const int cib_n = Cin / CI;
+    const int co0 = (blockIdx.x / cib_n) * CO, ci0 = (blockIdx.x % cib_n) * CI;
     const int split = blockIdx.y;
     const int HW = H * W;
     const int pbeg = split * pix_per_split, pend = min(P, pbeg + pix_per_split);
     const int r16 = lane & 15, k8 = (lane >> 4) * 8;
-    // 16-row blocks of co and ci that exist (the rest of the 64 x 64 block is padding)
-    const int ncob = min(4, (Cout - co0 + 15) / 16), ncib = min(4, (Cin - ci0 + 15) / 16);
-    f32x4 acc[3][4][4];
+    f32x4 acc[3][NCO][NCI];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < NCO; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[d][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j < NCI; ++j) acc[d][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero = {};
     for (int pk = pbeg; pk < pend; pk += kWgP) {
-        // stage dz: 16 pixel pairs x 8 channel octets
-        if (tid < 128) {
-            const int pair = tid >> 3, oct = tid & 7;
+        // stage dz: 16 pixel pairs x (2 NCO) channel octets
+        for (int t = tid; t < 16 * 2 * NCO; t += kWgThreads) {
+            const int pair = t / (2 * NCO), oct = t % (2 * NCO);
             const int p = pk + 2 * pair, co = co0 + 8 * oct;
             bf16x8 v0 = zero, v1 = zero;
-            if (co < Cout) {
-                if (p < pend) v0 = *reinterpret_cast<const bf16x8*>(dz + (size_t)p * zC + co);
-                if (p + 1 < pend) v1 = *reinterpret_cast<const bf16x8*>(dz + (size_t)(p + 1) * zC + co);
-            }
+            if (p < pend) v0 = *reinterpret_cast<const bf16x8*>(dz + (size_t)p * zC + co);
+            if (p + 1 < pend) v1 = *reinterpret_cast<const bf16x8*>(dz + (size_t)(p + 1) * zC + co);
 #pragma unroll
             for (int c = 0; c < 8; ++c)
                 *reinterpret_cast<unsigned*>(&sdz[(8 * oct + c) * kWgLd + 2 * pair]) =
                     bf16_bits(v0[c]) | (bf16_bits(v1[c]) << 16);
         }
-        // stage the nine shifted input tiles: 9 taps x 16 pixel pairs x 8 channel octets
-        for (int t = tid; t < 9 * 128; t += kWgThreads) {
-            const int tap = t >> 7, pair = (t >> 3) & 15, oct = t & 7;
+        // stage the nine shifted input tiles: 9 taps x 16 pixel pairs x (2 NCI) channel octets
+#pragma unroll 2
+        for (int t = tid; t < 9 * 16 * 2 * NCI; t += kWgThreads) {
+            const int tap = t / (32 * NCI), rest = t % (32 * NCI);
+            const int pair = rest / (2 * NCI), oct = rest % (2 * NCI);
             const int ci = ci0 + 8 * oct;
             bf16x8 v[2] = {zero, zero};
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int p = pk + 2 * pair + h;
-                if (p < pend && ci < Cin) {
+                if (p < pend) {
                     const int b = p / HW, rem = p - b * HW, py = rem / W, px = rem - py * W;
                     const int sy = py + tap / 3 - 1, sx2 = px + tap % 3 - 1;
                     if (sy >= 0 && sy < H && sx2 >= 0 && sx2 < W)
@@ -206,49 +207,45 @@ __global__ void __launch_bounds__(kWgThreads) k_wgrad(const bf16* __restrict__ d
                     bf16_bits(v[0][c]) | (bf16_bits(v[1][c]) << 16);
         }
         __syncthreads();
-        bf16x8 a[4];
+        bf16x8 a[NCO];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (i < ncob) a[i] = *reinterpret_cast<const bf16x8*>(&sdz[(16 * i + r16) * kWgLd + k8]);
+        for (int i = 0; i < NCO; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&sdz[(16 * i + r16) * kWgLd + k8]);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const bf16* xt = sx[3 * wave + d];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (j >= ncib) break;
+            for (int j = 0; j < NCI; ++j) {
                 const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&xt[(16 * j + r16) * kWgLd + k8]);
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (i < ncob) acc[d][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bv, acc[d][i][j], 0, 0, 0);
+                for (int i = 0; i < NCO; ++i)
+                    acc[d][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bv, acc[d][i][j], 0, 0, 0);
             }
         }
         __syncthreads();  // the next chunk overwrites the tiles
     }
-    float* out = part + (size_t)split * Cout * 9 * Cin;
+    // row of the result = output channel co0 + 16 i + 4 (lane / 16) + v, column = ci
+    float* out = part + (size_t)split * Cout * 9 * Cin + (size_t)(co0 + 4 * (lane >> 4)) * 9 * Cin + ci0 + r16;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const int tap = 3 * wave + d;
+    for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < NCO; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (i >= ncob || j >= ncib) continue;
-                const int ci = ci0 + 16 * j + r16;
+            for (int j = 0; j < NCI; ++j)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int co = co0 + 16 * i + 4 * (lane >> 4) + v;   // row of the result
-                    out[((size_t)co * 9 + tap) * Cin + ci] = acc[d][i][j][v];
-                }
-            }
-    }
+                for (int v = 0; v < 4; ++v)
+                    out[((size_t)(16 * i + v) * 9 + 3 * wave + d) * Cin + 16 * j] = acc[d][i][j][v];
 }
+
+// Largest 16-channel block count in {4, 2, 1} that divides n16 (channels / 16).
+inline int wgrad_blocks16(int n16) { return n16 % 4 == 0 ? 4 : (n16 % 2 == 0 ? 2 : 1); }
 
 // Pixels per split of the weight gradient of a layer with P pixels and the given padded
 // channel counts: about 512 workgroups (two per CU), at most 256 splits, at least 8
 // chunks each.
 inline int wgrad_pixels_per_split(size_t P, int cout16, int cin_pad)
 {
-    const size_t blocks = (size_t)((cout16 + 63) / 64) * ((cin_pad + 63) / 64);
+    const size_t blocks = (size_t)(cout16 / (16 * wgrad_blocks16(cout16 / 16))) *
+                          (cin_pad / (16 * wgrad_blocks16(cin_pad / 16)));
     size_t splits = std::min<size_t>(256, std::max<size_t>(1, 512 / blocks));
     splits = std::min(splits, std::max<size_t>(1, P / (8 * kWgP)));
     const size_t pps = (P + splits - 1) / splits;
@@ -813,9 +810,17 @@ clbm_status conv_backward(clbm_net* n, int k, TView dz)
     const int pps = wgrad_pixels_per_split((size_t)P, cout16, l.cin_pad);
     const int splits = (P + pps - 1) / pps;
     // weight gradient
-    hipLaunchKernelGGL(k_wgrad, dim3(((cout16 + 63) / 64) * ((l.cin_pad + 63) / 64), splits), dim3(kWgThreads),
-                       0, n->stream, dz.p, dz.C, cout16, l.in.p, l.in.C, l.in.off, l.cin_pad, l.H, l.W,
-                       P, pps, n->wpart);
+    const int nco = wgrad_blocks16(cout16 / 16), nci = wgrad_blocks16(l.cin_pad / 16);
+    const void* wg = nco == 4 ? (nci == 4 ? (const void*)&k_wgrad<4, 4> : nci == 2 ? (const void*)&k_wgrad<4, 2> : (const void*)&k_wgrad<4, 1>)
+                   : nco == 2 ? (nci == 4 ? (const void*)&k_wgrad<2, 4> : nci == 2 ? (const void*)&k_wgrad<2, 2> : (const void*)&k_wgrad<2, 1>)
+                              : (nci == 4 ? (const void*)&k_wgrad<1, 4> : nci == 2 ? (const void*)&k_wgrad<1, 2> : (const void*)&k_wgrad<1, 1>);
+    {
+        const bf16* zp = dz.p; int zc = dz.C, co = cout16; const bf16* xp = l.in.p; int xc = l.in.C, xo = l.in.off;
+        int ci = l.cin_pad, h = l.H, w = l.W, pp = P, ps = pps; float* pt = n->wpart;
+        void* args[] = {&zp, &zc, &co, &xp, &xc, &xo, &ci, &h, &w, &pp, &ps, &pt};
+        CLBM_HIP(hipLaunchKernel(wg, dim3((cout16 / (16 * nco)) * (l.cin_pad / (16 * nci)), splits),
+                                 dim3(kWgThreads), args, 0, n->stream));
+    }
     CLBM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_wgrad_reduce, grid1((size_t)cout16 * 9 * l.cin_pad), dim3(256), 0, n->stream,
                        n->wpart, splits, cout16, l.cin_pad, l.cout, l.cin, n->grads + l.woff);
