@@ -57,8 +57,10 @@ typedef enum {
     CLBM_ERR_UNSUPPORTED = -6       /* option not available for this configuration */
 } clbm_status;
 
-/* Population storage. Both store deviations from the rest state
- * (f_i - w_i and g_i - T0/5); the arithmetic is float32 in both. */
+/* Population storage. Both store deviations from the rest state (f_i - w_i and
+ * g_i - T0/5). The collision arithmetic is one step wider than the storage (FP64 for
+ * CLBM_FP32, FP32 for CLBM_FP16_SHIFTED) and every stored value is rounded without bias
+ * (stochastic rounding, its variates a hash of the node's coordinates and results). */
 typedef enum { CLBM_FP32 = 0, CLBM_FP16_SHIFTED = 1 } clbm_precision;
 
 typedef enum { CLBM_PERIODIC = 0, CLBM_WALL = 1 } clbm_side_kind;
