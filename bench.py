@@ -573,7 +573,7 @@ def main():
     ap.add_argument("--ws-max-steps-eval", type=int, default=3000000)
     ap.add_argument("--ws-grid", type=int, default=128)
     ap.add_argument("--ws-batch", type=int, default=32)
-    ap.add_argument("--ws-train-steps", type=int, default=3000)
+    ap.add_argument("--ws-train-steps", type=int, default=10000)
     ap.add_argument("--ws-eval", type=int, default=64)
     ap.add_argument("--ws-eval-side", type=int, default=512)
     ap.add_argument("--ws-save", default="", help="write the trained parameters (.npy)")
