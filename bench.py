@@ -655,7 +655,11 @@ def main():
                      "kernel": "k_step2" if spl == 2 else "k_step", "steps_per_launch": spl,
                      "kernel_avg_ms": round(kms, 5), "bytes_per_lup": bpl,
                      "copy_ceiling_GBs": round(copy_gbs, 1),
-                     "frac_of_copy": round(achieved / copy_gbs, 4)},
+                     "frac_of_copy": round(achieved / copy_gbs, 4),
+                     "note": ("achieved = algorithmic bytes of the launch's %d step(s) (%d B per node update) / "
+                              "launch time; with two steps per launch the intermediate state stays in LDS, so the "
+                              "launch moves about half of them: traffic (measured) / launch time = traffic_rate_GBs"
+                              % (spl, bpl))},
     }
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on the host")
