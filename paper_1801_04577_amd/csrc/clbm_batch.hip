@@ -61,6 +61,22 @@ __global__ void __launch_bounds__(1024) k_batch_step(const BatchInst* __restrict
     }
 }
 
+// Tile k of this workgroup among n active tiles (n when there is none). With at least 8
+// workgroups, the workgroups of XCD x (blockIdx % 8 == x) sweep the x-th of eight
+// contiguous bands of the list (instance by instance, row by row), so the ring nodes that
+// neighbouring tiles of an instance share stay in that XCD's L2.
+__device__ __forceinline__ int banded_tile(int k, int n)
+{
+    const int b = blockIdx.x, G = gridDim.x;
+    if (G < 8) {
+        const int t = b + k * G;
+        return t < n ? t : n;
+    }
+    const int x = b & 7, i = b >> 3, per = (G - x + 7) >> 3, band = (n + 7) >> 3;
+    const int j = i + k * per, t = x * band + j;
+    return j < band && t < n ? t : n;
+}
+
 // Two time steps of every instance on the active tile list (tiles of kBlock x
 // kTwoStepRows nodes, grid-stride over tiles; the LDS tile is reused by each tile a
 // workgroup takes). Per tile it runs the phases of k_step2, so two steps here are two
@@ -77,7 +93,9 @@ __global__ void __launch_bounds__(kTwoStepThreads) __attribute__((amdgpu_waves_p
     __shared__ float tile[14 * Tile2<TY>::P];
     const int n = uniform_int(*count);
     const int tid = (int)threadIdx.x;
-    for (int t = blockIdx.x; t < n; t += gridDim.x) {
+    for (int k = 0;; ++k) {
+        const int t = banded_tile(k, n);
+        if (t >= n) break;
         const int2 e = list[t];
         const int inst = uniform_int(e.x), id = uniform_int(e.y);
         const BatchInst& I = insts[inst];
