@@ -131,6 +131,103 @@ __global__ void __launch_bounds__(256) k_conv(const bf16* __restrict__ x, int xC
     }
 }
 
+// The same convolution with both operands staged in LDS. A workgroup owns a block of
+// BH x BW pixels of one image (BH = 256 / BW; wave w owns pixels 64 w .. 64 w + 63 of the
+// block in row-major order, as four MFMA blocks of 16) and 16 NB output channels. Per
+// chunk of 32 input channels it stages the block with its one-pixel halo and the weights
+// of the nine taps in LDS, pixel-major (resp. channel-major) with the 32 channels of the
+// chunk contiguous, so each tap reads both operands from LDS at compile-time offsets:
+// an activation is fetched from memory once per chunk instead of once per tap, and a
+// weight once per workgroup instead of once per wave.
+constexpr int kCvLd = 32;   // LDS row: the 32 channels of a chunk
+
+template <int NB, int BW>
+__global__ void __launch_bounds__(256) k_conv_lds(const bf16* __restrict__ x, int xC, int xoff, int Cin,
+                                                  const bf16* __restrict__ w,
+                                                  const float* __restrict__ bias, int N, int H, int W,
+                                                  int mode, bf16* __restrict__ y, int yC, int yoff,
+                                                  float* __restrict__ yf)
+{
+    constexpr int BH = 256 / BW, HX = BW + 2, HY = BH + 2, NPIX = HX * HY, NC = 16 * NB;
+    __shared__ __attribute__((aligned(16))) bf16 sa[NPIX * kCvLd];
+    __shared__ __attribute__((aligned(16))) bf16 sw[9 * NC * kCvLd];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int bx_n = W / BW, by_n = H / BH;
+    const int bxi = blockIdx.x % bx_n, byi = (blockIdx.x / bx_n) % by_n, bimg = blockIdx.x / (bx_n * by_n);
+    const int x0 = bxi * BW, y0 = byi * BH;
+    const int n0 = blockIdx.y * NC;
+    const int r16 = lane & 15, k8 = (lane >> 4) * 8;
+    // LDS element of the A row of each of the wave's four pixel blocks at tap 0 (the
+    // top-left neighbour); tap t adds ((t / 3) HX + t % 3) rows
+    int abase[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int q = wave * 64 + 16 * j + r16;
+        abase[j] = ((q / BW) * HX + (q % BW)) * kCvLd + k8;
+    }
+    f32x4 acc[4][NB];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[j][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero = {};
+    for (int c0 = 0; c0 < Cin; c0 += kKChunk) {
+        for (int t = tid; t < NPIX * 4; t += 256) {
+            const int px = t >> 2, oct = t & 3;
+            const int hy = px / HX, hx = px - hy * HX;
+            const int sy = y0 + hy - 1, sx = x0 + hx - 1;
+            bf16x8 v = zero;
+            if (sy >= 0 && sy < H && sx >= 0 && sx < W)
+                v = *reinterpret_cast<const bf16x8*>(x + ((size_t)(bimg * H + sy) * W + sx) * xC + xoff + c0 + 8 * oct);
+            *reinterpret_cast<bf16x8*>(&sa[px * kCvLd + 8 * oct]) = v;
+        }
+        for (int t = tid; t < 9 * NC * 4; t += 256) {
+            const int oct = t & 3, rest = t >> 2;   // rest = tap * NC + channel
+            const int tap = rest / NC, nn = rest - tap * NC;
+            *reinterpret_cast<bf16x8*>(&sw[rest * kCvLd + 8 * oct]) =
+                *reinterpret_cast<const bf16x8*>(w + ((size_t)(n0 + nn) * 9 + tap) * Cin + c0 + 8 * oct);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int off = ((tap / 3) * HX + tap % 3) * kCvLd;
+            bf16x8 a[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a[j] = *reinterpret_cast<const bf16x8*>(&sa[abase[j] + off]);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const bf16x8 bw = *reinterpret_cast<const bf16x8*>(&sw[(tap * NC + 16 * nb + r16) * kCvLd + k8]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j], bw, acc[j][nb], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // the next chunk overwrites the tiles
+    }
+    const int HW = H * W;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int n = n0 + 16 * nb + r16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int q = wave * 64 + 16 * j + 4 * (lane >> 4) + v;
+            const int p = (bimg * H + y0 + q / BW) * W + x0 + q % BW;
+            float r = acc[j][nb][v];
+            if (mode == 2) {
+                if (n < N) {
+                    const int bb = p / HW, rr = p - bb * HW;
+                    yf[((size_t)bb * N + n) * HW + rr] = r + bias[n];
+                }
+            } else if (n < N) {
+                if (mode == 0) r = fmaxf(r + bias[n], 0.f);
+                y[(size_t)p * yC + yoff + n] = f2bf(r);
+            }
+        }
+    }
+}
+
 // Weight gradient of one 3x3 convolution over a range of pixels (split-K):
 // part[s][co][tap][ci] = sum over the pixels p of split s of dz[p][co] * x[src(p,tap)][ci],
 // a GEMM whose reduction runs over pixels, the slow index of NHWC. A workgroup of three
@@ -747,6 +844,18 @@ clbm_status conv_launch(clbm_net* n, const Layer& l, TView in, int cin_pad, cons
                         const float* bias, int N, int nb, int npad, int mode, TView out, float* yf)
 {
     const int P = n->d.batch * l.H * l.W;
+    int xC = in.C, xoff = in.off, Cin = cin_pad, H = l.H, W = l.W, yC = out.C, yoff = out.off;
+    const bf16* x = in.p;
+    bf16* y = out.p;
+    void* args[] = {&x, &xC, &xoff, &Cin, (void*)&w, (void*)&bias, &N, &H, &W, &mode, &y, &yC, &yoff, &yf};
+    // LDS-staged kernel: pixel blocks of 256 (BW = 64, 32 or 16 columns) that tile the image
+    const int bw = W >= 64 ? 64 : W;
+    if ((nb == 4 || nb == 2) && (bw == 64 || bw == 32 || bw == 16) && W % bw == 0 && H % (256 / bw) == 0) {
+        const void* fl = nb == 4 ? (bw == 64 ? (const void*)&k_conv_lds<4, 64> : bw == 32 ? (const void*)&k_conv_lds<4, 32> : (const void*)&k_conv_lds<4, 16>)
+                                 : (bw == 64 ? (const void*)&k_conv_lds<2, 64> : bw == 32 ? (const void*)&k_conv_lds<2, 32> : (const void*)&k_conv_lds<2, 16>);
+        CLBM_HIP(hipLaunchKernel(fl, dim3(P / 256, npad / (16 * nb)), dim3(256), args, 0, n->stream));
+        return CLBM_OK;
+    }
     // four 16-pixel blocks per wave where the pixel count allows (it is a multiple of 64)
     const int mp = P % 256 == 0 ? 4 : 1;
     const dim3 grid(P / (64 * mp), npad / (16 * nb));
@@ -757,10 +866,6 @@ clbm_status conv_launch(clbm_net* n, const Layer& l, TView in, int cin_pad, cons
                 : (nb == 4 ? reinterpret_cast<const void*>(&k_conv<4, 1>)
                   : nb == 2 ? reinterpret_cast<const void*>(&k_conv<2, 1>)
                             : reinterpret_cast<const void*>(&k_conv<1, 1>));
-    int xC = in.C, xoff = in.off, Cin = cin_pad, H = l.H, W = l.W, yC = out.C, yoff = out.off;
-    const bf16* x = in.p;
-    bf16* y = out.p;
-    void* args[] = {&x, &xC, &xoff, &Cin, (void*)&w, (void*)&bias, &N, &H, &W, &mode, &y, &yC, &yoff, &yf};
     CLBM_HIP(hipLaunchKernel(fn, grid, dim3(256), args, 0, n->stream));
     return CLBM_OK;
 }
