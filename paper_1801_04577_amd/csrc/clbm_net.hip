@@ -171,23 +171,47 @@ __global__ void __launch_bounds__(256) k_conv_lds(const bf16* __restrict__ x, in
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[j][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero = {};
-    for (int c0 = 0; c0 < Cin; c0 += kKChunk) {
-        for (int t = tid; t < NPIX * 4; t += 256) {
-            const int px = t >> 2, oct = t & 3;
-            const int hy = px / HX, hx = px - hy * HX;
-            const int sy = y0 + hy - 1, sx = x0 + hx - 1;
-            bf16x8 v = zero;
-            if (sy >= 0 && sy < H && sx >= 0 && sx < W)
-                v = *reinterpret_cast<const bf16x8*>(x + ((size_t)(bimg * H + sy) * W + sx) * xC + xoff + c0 + 8 * oct);
-            *reinterpret_cast<bf16x8*>(&sa[px * kCvLd + 8 * oct]) = v;
+    // The next chunk's operands are loaded into registers while the current one is
+    // multiplied from LDS.
+    constexpr int NA = (NPIX * 4 + 255) / 256, NWT = (9 * NC * 4 + 255) / 256;
+    bf16x8 ra[NA], rw[NWT];
+    auto load_chunk = [&](int c0) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int t = tid + 256 * i;
+            ra[i] = zero;
+            if (t < NPIX * 4) {
+                const int px = t >> 2, oct = t & 3;
+                const int hy = px / HX, hx = px - hy * HX;
+                const int sy = y0 + hy - 1, sx = x0 + hx - 1;
+                if (sy >= 0 && sy < H && sx >= 0 && sx < W)
+                    ra[i] = *reinterpret_cast<const bf16x8*>(x + ((size_t)(bimg * H + sy) * W + sx) * xC + xoff + c0 + 8 * oct);
+            }
         }
-        for (int t = tid; t < 9 * NC * 4; t += 256) {
-            const int oct = t & 3, rest = t >> 2;   // rest = tap * NC + channel
-            const int tap = rest / NC, nn = rest - tap * NC;
-            *reinterpret_cast<bf16x8*>(&sw[rest * kCvLd + 8 * oct]) =
-                *reinterpret_cast<const bf16x8*>(w + ((size_t)(n0 + nn) * 9 + tap) * Cin + c0 + 8 * oct);
+#pragma unroll
+        for (int i = 0; i < NWT; ++i) {
+            const int t = tid + 256 * i;
+            if (t < 9 * NC * 4) {
+                const int oct = t & 3, rest = t >> 2;   // rest = tap * NC + channel
+                const int tap = rest / NC, nn = rest - tap * NC;
+                rw[i] = *reinterpret_cast<const bf16x8*>(w + ((size_t)(n0 + nn) * 9 + tap) * Cin + c0 + 8 * oct);
+            }
+        }
+    };
+    load_chunk(0);
+    for (int c0 = 0; c0 < Cin; c0 += kKChunk) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int t = tid + 256 * i;
+            if (t < NPIX * 4) *reinterpret_cast<bf16x8*>(&sa[(t >> 2) * kCvLd + 8 * (t & 3)]) = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NWT; ++i) {
+            const int t = tid + 256 * i;
+            if (t < 9 * NC * 4) *reinterpret_cast<bf16x8*>(&sw[(t >> 2) * kCvLd + 8 * (t & 3)]) = rw[i];
         }
         __syncthreads();
+        if (c0 + kKChunk < Cin) load_chunk(c0 + kKChunk);
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int off = ((tap / 3) * HX + tap % 3) * kCvLd;
