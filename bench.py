@@ -377,6 +377,46 @@ def net_flops_per_sample(H, W, cin=8, cout=3, widths=(32, 64, 128, 256)):
     return sum(2.0 * (H // r) * (W // r) * 9 * ci * co for r, ci, co in layers)
 
 
+def net_throughput(args):
+    """Throughput of the warm-start network's kernels alone: forward passes, and training
+    steps (forward, backward, Adam) at the benchmark's batch on its grid, random inputs and
+    targets (the kernels' cost does not depend on the values)."""
+    import numpy as np
+    import torch
+    import paper_1801_04577_amd as clbm
+    from paper_1801_04577_amd import warmstart as ws
+    B, G = args.ws_batch, args.ws_grid
+    net = clbm.Net(B, G, G, ws.CIN, ws.COUT, ws.WIDTHS)
+    net.set_params(torch.from_numpy(ws.init_params(seed=0)))
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    X = torch.randn(B, ws.CIN, G, G, device="cuda", generator=gen)
+    Y = torch.randn(B, ws.COUT, G, G, device="cuda", generator=gen)
+    for t in range(1, 6):
+        net.forward(X)
+        net.backward(Y)
+        net.adam(1e-3, t)
+    n = args.net_steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(6, 6 + n):
+        net.forward(X)
+        net.backward(Y)
+        net.adam(1e-3, t)
+    torch.cuda.synchronize()
+    dt_train = (time.perf_counter() - t0) / n
+    t0 = time.perf_counter()
+    for _ in range(n):
+        net.forward(X)
+    torch.cuda.synchronize()
+    dt_fwd = (time.perf_counter() - t0) / n
+    fl = net_flops_per_sample(G, G) * B
+    return {"batch": B, "grid": G, "steps": n,
+            "train_ms_per_step": round(dt_train * 1e3, 3), "train_tflops": round(3.0 * fl / dt_train / 1e12, 1),
+            "forward_ms": round(dt_fwd * 1e3, 3), "forward_tflops": round(fl / dt_fwd / 1e12, 1),
+            "flops_note": "3x3 convolutions only; a training step counts 3x the forward flops",
+            "mfma_peak_tflops_bf16": 2500.0}
+
+
 def train_network(args, res, net, grid, progress):
     """Training half of the warm-start experiment: steady states of the training cavities
     from the batched solver (cold starts to residual 1e-7), then Adam on the network."""
@@ -566,6 +606,8 @@ def main():
     ap.add_argument("--sweep-max-steps", type=int, default=200000)
     ap.add_argument("--write-cache", default="", help="path of the autotuner cache (JSON lines)")
     ap.add_argument("--warmstart", action="store_true", help="run the learned warm-start experiment only")
+    ap.add_argument("--net", action="store_true", help="time the warm-start network's kernels only")
+    ap.add_argument("--net-steps", type=int, default=50)
     ap.add_argument("--ws-train", type=int, default=2000)
     ap.add_argument("--ws-train-sides", default="64,96,128")
     ap.add_argument("--ws-chunk-instances", type=int, default=1024)
@@ -600,6 +642,9 @@ def main():
         return
     if args.configs:
         print(json.dumps({"metric": METRIC, "configs": small_configs(args)}), flush=True)
+        return
+    if args.net:
+        print(json.dumps({"metric": METRIC, "network": net_throughput(args)}), flush=True)
         return
     if args.warmstart:
         r = warmstart_experiment(args)
