@@ -259,19 +259,26 @@ __device__ __forceinline__ void collide(const LatticeConst& c, const float a_in[
     const R inv = recip(rho);
     const R ux = (jx + R(0.5) * Fx) * inv;
     const R uy = (jy + R(0.5) * Fy) * inv;
-    const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+    const R tx = R(2) * ux, ty = R(2) * uy, ux2 = ux * ux, uy2 = uy * uy;
 
-    // Central moments (Eq. 6b) of the relaxed orders, minus their equilibria (Eq. 9).
-    const R K20 = third + k20;                  // full raw k20
-    const R K02 = third + k02;
-    const R n20 = (k20 - d * third) - R(2) * ux * jx + ux2 * rho;
-    const R n02 = (k02 - d * third) - R(2) * uy * jy + uy2 * rho;
-    const R c11 = k11 - uy * jx - ux * jy + uxy * rho;
-    const R c21 = k21 - R(2) * ux * k11 - uy * K20 + R(2) * uxy * jx + ux2 * jy - ux2 * uy * rho;
-    const R c12 = k12 - R(2) * uy * k11 - ux * K02 + R(2) * uxy * jy + uy2 * jx - uy2 * ux * rho;
-    const R n22 = (k22 - d * ninth) - R(2) * ux * k12 - R(2) * uy * k21 + R(4) * uxy * k11
-                  + uy2 * K20 + ux2 * K02 - R(2) * ux * uy2 * jx - R(2) * ux2 * uy * jy
-                  + ux2 * uy2 * rho;
+    // Central moments (Eq. 6b) of the relaxed orders, minus their equilibria (Eq. 9). The
+    // shift N(u) factors into one-dimensional binomial shifts: along x on each row of
+    // moments, h_mn = sum (e_x - u_x)^m e_y^n f, then along y on each column. The first
+    // x moment is h_10 = j_x - u_x rho = -F_x/2 by Eq. (12) (and h_01 = -F_y/2 along y).
+    // Terms that cancel against the equilibria are taken from the deviations first.
+    const R K02 = third + k02;                  // full raw k02
+    const R n20 = (k20 - d * third) - tx * jx + ux2 * rho;    // c20 - rho/3 = h20 - rho/3
+    const R h20 = n20 + third * rho;
+    const R h10 = R(-0.5) * Fx;
+    const R h11 = k11 - ux * jy;
+    const R h21 = (k21 - tx * k11) + ux2 * jy;
+    const R h12 = k12 - ux * K02;
+    const R h22 = ((k22 - d * ninth) - tx * k12) + ux2 * K02;  // h22 - rho/9
+    const R n02 = (k02 - d * third) - ty * jy + uy2 * rho;
+    const R c11 = h11 - uy * h10;
+    const R c21 = h21 - uy * h20;
+    const R c12 = (h12 - ty * h11) + uy2 * h10;
+    const R n22 = (h22 - ty * h21) + uy2 * h20;
 
     // Eq. (7): changes of the central moments; on k10, k01 the change is the force.
     const R sp = kv<R>(c.sp, c.d_sp), sm = kv<R>(c.sm, c.d_sm);
@@ -283,14 +290,19 @@ __device__ __forceinline__ void collide(const LatticeConst& c, const float a_in[
     const R D12 = h3 * Fx - s3 * c12;
     const R D22 = -kv<R>(c.s4, c.d_s4) * n22;
 
-    // Shift by -u (inverse of Eq. 6b); Delta k00 = 0.
-    const R R20 = D20 + R(2) * ux * Fx;
-    const R R02 = D02 + R(2) * uy * Fy;
-    const R R11 = D11 + uy * Fx + ux * Fy;
-    const R R21 = D21 + R(2) * ux * D11 + uy * D20 + R(2) * uxy * Fx + ux2 * Fy;
-    const R R12 = D12 + R(2) * uy * D11 + ux * D02 + R(2) * uxy * Fy + uy2 * Fx;
-    const R R22 = D22 + R(2) * ux * D12 + R(2) * uy * D21 + R(4) * uxy * D11 + uy2 * D20 + ux2 * D02
-                  + R(2) * uxy * (uy * Fx + ux * Fy);
+    // Shift by -u (inverse of Eq. 6b), along y on each column of changes, then along x on
+    // each row; Delta k00 = 0, Delta k10 = F_x, Delta k01 = F_y.
+    const R g11 = D11 + uy * Fx;
+    const R g21 = D21 + uy * D20;
+    const R g02 = D02 + ty * Fy;
+    const R g12 = (D12 + ty * D11) + uy2 * Fx;
+    const R g22 = (D22 + ty * D21) + uy2 * D20;
+    const R R20 = D20 + tx * Fx;
+    const R R02 = g02;
+    const R R11 = g11 + ux * Fy;
+    const R R21 = (g21 + tx * g11) + ux2 * Fy;
+    const R R12 = g12 + ux * g02;
+    const R R22 = (g22 + tx * g12) + ux2 * g02;
 
     // Inverse of Eq. (6a), added to the incoming populations.
     const R v1 = R20 - R22, u1 = Fx - R12;
