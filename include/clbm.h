@@ -76,7 +76,11 @@ typedef struct {
 } clbm_side;
 
 typedef struct {
-    int nx, ny;         /* lattice nodes; >= 2 across walled directions */
+    int nx, ny;         /* lattice nodes; >= 2 across walled directions. Limits (else
+                           CLBM_ERR_UNSUPPORTED): 14 x 64 ceil(nx/64) x 4 bytes < 2^32 (nx up
+                           to about 76 million) and the lattice padded to 64 x 4 blocks
+                           holds fewer than 2^32 nodes; beyond that only device memory
+                           bounds the size (112 B per node in FP32, 56 B in FP16). */
     int precision;      /* clbm_precision */
     double nu;          /* kinematic viscosity: s_nu = 1/(3 nu + 1/2) (Sec. 2.1) */
     double alpha;       /* thermal diffusivity: lambda_1 = 1/(alpha/c_T^2 + 1/2) (Sec. 2.2) */
@@ -224,7 +228,9 @@ typedef struct {
     int steps_per_launch;
 } clbm_batch_launch;
 
-/* Host only. Workspace for n instances (all precision fields must be CLBM_FP32). */
+/* Host only. Workspace for n instances (all precision fields must be CLBM_FP32; each
+ * instance's population buffer, 14 x 64 ceil(nx/64) x ny values, must hold fewer than
+ * 2^32 of them, else CLBM_ERR_UNSUPPORTED). */
 clbm_status clbm_batch_workspace_bytes(int n, const clbm_params* p, size_t* bytes);
 /* launch NULL selects the default shape. */
 clbm_status clbm_batch_create(int n, const clbm_params* p, void* d_workspace, size_t bytes,

@@ -6,6 +6,17 @@
 
 namespace clbm {
 
+// Node (x, y) of this thread under a one-dimensional grid of blockDim.x x blockDim.y
+// blocks that cover the lattice row of blocks by row of blocks (a one-dimensional grid
+// has no per-dimension limit on the block count).
+__device__ __forceinline__ void grid_node(const LatticeConst& c, int& x, int& y)
+{
+    const unsigned nbx = ((unsigned)c.nx + blockDim.x - 1) / blockDim.x;
+    const unsigned by = blockIdx.x / nbx, bx = blockIdx.x - by * nbx;
+    x = (int)(bx * blockDim.x + threadIdx.x);
+    y = (int)(by * blockDim.y + threadIdx.y);
+}
+
 // Equilibrium at the given fields followed by one collision: the stored state is
 // the post-collision state at t = 0.
 template <typename S>
@@ -15,8 +26,8 @@ __global__ void __launch_bounds__(256) k_init(S* __restrict__ dst, const Lattice
                                               const float* __restrict__ uy,
                                               const float* __restrict__ T)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    int x, y;
+    grid_node(c, x, y);
     if (x >= c.nx || y >= c.ny) return;
     const size_t k = (size_t)y * c.nx + x;
     const float drho = rho ? rho[k] - 1.f : 0.f;
@@ -37,8 +48,8 @@ __global__ void __launch_bounds__(256) k_macros(const S* __restrict__ src, const
                                                 float* __restrict__ rho, float* __restrict__ ux,
                                                 float* __restrict__ uy, float* __restrict__ T)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    int x, y;
+    grid_node(c, x, y);
     if (x >= c.nx || y >= c.ny) return;
     float a[9], b[5];
     load_own(src, c, node_off(c, x, y), a, b);
@@ -54,10 +65,10 @@ template <typename S>
 __global__ void __launch_bounds__(256) k_populations(const S* __restrict__ src, const LatticeConst c,
                                                      float* __restrict__ f, float* __restrict__ g)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    int x, y;
+    grid_node(c, x, y);
     if (x >= c.nx || y >= c.ny) return;
-    const unsigned own = node_off(c, x, y);
+    const size_t own = node_off(c, x, y);
     const size_t n = (size_t)c.nx * c.ny, k = (size_t)y * c.nx + x;
     if (f)
         for (int i = 0; i < 9; ++i) f[i * n + k] = ld(src + i * kBlock + own);
@@ -93,7 +104,7 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag(const S* __restrict__ src, 
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
         const int y = (int)(k / c.nx), x = (int)(k - (size_t)y * c.nx);
-        const unsigned own = node_off(c, x, y);
+        const size_t own = node_off(c, x, y);
         float a[9], b[5];
         load_own(src, c, own, a, b);
         const NodeMacro m = c.viscous ? macros_from_post<true>(c, a, b) : macros_from_post(c, a, b);
@@ -119,7 +130,7 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag(const S* __restrict__ src, 
             if (!wall[s]) continue;
             const int x2 = s == 0 ? x + 1 : (s == 1 ? x - 1 : x);
             const int y2 = s == 2 ? y + 1 : (s == 3 ? y - 1 : y);
-            const unsigned o2 = node_off(c, x2, y2);
+            const size_t o2 = node_off(c, x2, y2);
             const float th2 = c.viscous ? theta_post<S, true>(src, c, o2) : theta_post<S, false>(src, c, o2);
             const float thw = c.a1[s] * m.theta + c.a2[s] * th2 + c.a3[s];
             acc[5 + s] += (8.0 * thw - 9.0 * m.theta + th2) / 3.0;

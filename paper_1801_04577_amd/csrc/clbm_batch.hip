@@ -50,13 +50,13 @@ __global__ void __launch_bounds__(1024) k_batch_step(const BatchInst* __restrict
             double fa[9], tb[5];
             NodeMacro m;
             if (c.viscous) {
-                gather_node<float, true>(src, c, x, y, a, b);
+                gather_node<float, true, unsigned>(src, c, x, y, a, b);
                 collide<double, true>(c, a, b, fa, tb, m);
             } else {
-                gather_node(src, c, x, y, a, b);
+                gather_node<float, false, unsigned>(src, c, x, y, a, b);
                 collide(c, a, b, fa, tb, m);
             }
-            store_node(dst, c, x, y, fa, tb);
+            store_node<float, unsigned>(dst, c, x, y, fa, tb);
         }
     }
 }
@@ -105,13 +105,13 @@ __global__ void __launch_bounds__(kTwoStepThreads) __attribute__((amdgpu_waves_p
         const float* src = reinterpret_cast<const float*>(I.buf[parity]);
         float* dst = reinterpret_cast<float*>(I.buf[parity ^ 1]);
         if (VH == 1 || (VH == 2 && c.viscous)) {
-            step2_phase1<float, true, TY, NT>(src, c, tile, X0, Y0, tid);
+            step2_phase1<float, true, TY, NT, unsigned>(src, c, tile, X0, Y0, tid);
             __syncthreads();
-            step2_phase2<float, true, TY, NT>(dst, c, tile, X0, Y0, tid);
+            step2_phase2<float, true, TY, NT, unsigned>(dst, c, tile, X0, Y0, tid);
         } else {
-            step2_phase1<float, false, TY, NT>(src, c, tile, X0, Y0, tid);
+            step2_phase1<float, false, TY, NT, unsigned>(src, c, tile, X0, Y0, tid);
             __syncthreads();
-            step2_phase2<float, false, TY, NT>(dst, c, tile, X0, Y0, tid);
+            step2_phase2<float, false, TY, NT, unsigned>(dst, c, tile, X0, Y0, tid);
         }
         __syncthreads();  // the next tile overwrites the LDS tile
     }
@@ -370,6 +370,8 @@ clbm_status batch_layout(int n, const clbm_params* p, BatchLayout* L)
         if (p[i].precision != CLBM_FP32) return CLBM_ERR_UNSUPPORTED;
         clbm_status st = validate(&p[i], nullptr);
         if (st != CLBM_OK) return st;
+        // the batched kernels address an instance with 32-bit element offsets
+        if (buffer_elems(p[i].nx, p[i].ny) >= 0xFFFFFFFFull) return CLBM_ERR_UNSUPPORTED;
         cap += (long long)((p[i].nx + kMinTileX - 1) / kMinTileX) * p[i].ny;
     }
     if (cap >= (1LL << 30)) return CLBM_ERR_UNSUPPORTED;
@@ -655,7 +657,7 @@ clbm_status clbm_batch_init(clbm_batch* b, int i, const float* d_rho, const floa
     if (!b || i < 0 || i >= b->n) return CLBM_ERR_INVALID_ARG;
     const BatchInst& I = b->inst[i];
     const dim3 blk(64, 4);
-    const dim3 grd((I.c.nx + 63) / 64, (I.c.ny + 3) / 4);
+    const dim3 grd = node_grid(I.c, blk);
     // the current buffer of the batch (all instances share the parity)
     hipLaunchKernelGGL(k_init<float>, grd, blk, 0, b->stream, (float*)(uintptr_t)I.buf[b->parity],
                        I.c, d_rho, d_ux, d_uy, d_T);
@@ -717,7 +719,7 @@ clbm_status clbm_batch_macros(clbm_batch* b, int i, float* d_rho, float* d_ux, f
     if (!b || i < 0 || i >= b->n) return CLBM_ERR_INVALID_ARG;
     const BatchInst& I = b->inst[i];
     const dim3 blk(64, 4);
-    const dim3 grd((I.c.nx + 63) / 64, (I.c.ny + 3) / 4);
+    const dim3 grd = node_grid(I.c, blk);
     hipLaunchKernelGGL(k_macros<float>, grd, blk, 0, b->stream,
                        (const float*)(uintptr_t)I.buf[b->parity], I.c, d_rho, d_ux, d_uy, d_T);
     CLBM_HIP(hipGetLastError());

@@ -76,9 +76,10 @@ __device__ __forceinline__ float recip(float x)
 }
 
 // Element offset of population 0 of node (x, y); population i is kBlock * i further.
-__device__ __forceinline__ unsigned node_off(const LatticeConst& c, int x, int y)
+// 64-bit: a buffer may hold more than 2^32 elements (a row holds fewer).
+__device__ __forceinline__ size_t node_off(const LatticeConst& c, int x, int y)
 {
-    return (unsigned)y * c.rowlen + ((unsigned)x / kBlock) * kBlockElems + ((unsigned)x % kBlock);
+    return (size_t)(unsigned)y * c.rowlen + ((unsigned)x / kBlock) * kBlockElems + ((unsigned)x % kBlock);
 }
 
 // Storage loads: float32 or binary16.

@@ -49,5 +49,8 @@ LatticeConst make_const(const clbm_params* p, const Rates& r);
 // population buffer (ny rows).
 size_t row_elems(int nx);
 size_t buffer_elems(int nx, int ny);
+// One-dimensional grid of blk-shaped blocks covering a lattice, for the per-node kernels
+// (grid_node decodes a block index into its nodes).
+dim3 node_grid(const LatticeConst& c, dim3 blk);
 
 }  // namespace clbm

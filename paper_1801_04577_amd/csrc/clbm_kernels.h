@@ -17,19 +17,22 @@ namespace clbm {
 // the two-step kernel, the workgroup's tile in LDS (TileMem). Each gives the element
 // offset of a neighbour's row and column part and the stride P between the populations
 // of one node. In a periodic direction GlobalMem wraps the neighbour; TileMem does not,
-// since its halo already holds the wrapped nodes.
-template <typename S>
+// since its halo already holds the wrapped nodes. Element offsets into the stored buffer
+// have the type O: 32-bit where the buffer holds fewer than 2^32 elements, else 64-bit
+// (the host picks the kernel); offsets within a row and in LDS are 32-bit.
+template <typename S, typename O = size_t>
 struct GlobalMem {
     typedef S Elem;
+    typedef O Off;
     const S* __restrict__ p;
     unsigned rowlen;
     int nx, ny;
     static constexpr unsigned P = kBlock;
-    __device__ __forceinline__ unsigned row(int y, int d) const
+    __device__ __forceinline__ Off row(int y, int d) const
     {
         int yy = y + d;
         yy = yy < 0 ? ny - 1 : (yy >= ny ? 0 : yy);
-        return (unsigned)yy * rowlen;
+        return (Off)(unsigned)yy * rowlen;
     }
     __device__ __forceinline__ unsigned col(int x, int d) const
     {
@@ -39,15 +42,15 @@ struct GlobalMem {
     }
 };
 
-template <typename S>
-__device__ __forceinline__ GlobalMem<S> global_mem(const S* __restrict__ src, const LatticeConst& c)
+template <typename O = size_t, typename S>
+__device__ __forceinline__ GlobalMem<S, O> global_mem(const S* __restrict__ src, const LatticeConst& c)
 {
-    return GlobalMem<S>{src, c.rowlen, c.nx, c.ny};
+    return GlobalMem<S, O>{src, c.rowlen, c.nx, c.ny};
 }
 
 // The 14 populations of the node at offset own.
-template <typename S, unsigned P>
-__device__ __forceinline__ void load_pops(const S* p, unsigned own, float a[9], float b[5])
+template <typename S, unsigned P, typename Off>
+__device__ __forceinline__ void load_pops(const S* p, Off own, float a[9], float b[5])
 {
 #pragma unroll
     for (int i = 0; i < 9; ++i) a[i] = ld(p + i * P + own);
@@ -58,15 +61,15 @@ __device__ __forceinline__ void load_pops(const S* p, unsigned own, float a[9], 
 // The 14 stored populations of one node (own = node_off).
 template <typename S>
 __device__ __forceinline__ void load_own(const S* __restrict__ src, const LatticeConst& c,
-                                         unsigned own, float a[9], float b[5])
+                                         size_t own, float a[9], float b[5])
 {
     load_pops<S, kBlock>(src, own, a, b);
 }
 
 // T - T0 at time t of the node at element offset off, from its post-collision
 // populations: sum g* - Q/2, with Q the node's own source under VH.
-template <bool VH, typename S, unsigned P>
-__device__ __forceinline__ float theta_at(const S* p, const LatticeConst& c, unsigned off)
+template <bool VH, typename S, unsigned P, typename Off>
+__device__ __forceinline__ float theta_at(const S* p, const LatticeConst& c, Off off)
 {
     const S* gs = p + 9 * P;
     if constexpr (VH) {
@@ -82,7 +85,7 @@ __device__ __forceinline__ float theta_at(const S* p, const LatticeConst& c, uns
 
 template <typename S, bool VH>
 __device__ __forceinline__ float theta_post(const S* __restrict__ src, const LatticeConst& c,
-                                            unsigned off)
+                                            size_t off)
 {
     return theta_at<VH, S, kBlock>(src, c, off);
 }
@@ -96,15 +99,17 @@ __device__ __forceinline__ void gather_mem(const Mem& mem, const LatticeConst& c
                                            float a[9], float b[5])
 {
     constexpr unsigned P = Mem::P;
+    typedef typename Mem::Off Off;
     // A link whose source lies outside a wall is flagged, and its source is the node
     // itself (the address is never used).
     const bool oxm = !c.periodic_x && x == 0, oxp = !c.periodic_x && x == c.nx - 1;
     const bool oym = !c.periodic_y && y == 0, oyp = !c.periodic_y && y == c.ny - 1;
     // Offsets of the three source rows and the three source columns.
-    const unsigned rC = mem.row(y, 0), cC = mem.col(x, 0);
-    const unsigned rM = oym ? rC : mem.row(y, -1), rP = oyp ? rC : mem.row(y, 1);
+    const Off rC = mem.row(y, 0);
+    const unsigned cC = mem.col(x, 0);
+    const Off rM = oym ? rC : mem.row(y, -1), rP = oyp ? rC : mem.row(y, 1);
     const unsigned cM = oxm ? cC : mem.col(x, -1), cP = oxp ? cC : mem.col(x, 1);
-    const unsigned own = rC + cC;
+    const Off own = rC + cC;
     const auto* src = mem.p;
 
     // Eq. (11) pull form f_i(x, t+1) = f_i*(x - e_i, t); a wall link takes the
@@ -130,7 +135,7 @@ __device__ __forceinline__ void gather_mem(const Mem& mem, const LatticeConst& c
         // Eq. (26): g_i(x_f, t+1) = -g*_opp(i)(x_f, t) + c_T^2 T_w, with T_w from Eq. (28)
         // using T at this node (T1) and one node further from the wall (T2) at time t.
         // Post-collision data give T = sum g* - Q/2 (the collision adds Q).
-        auto theta = [&](unsigned off) { return theta_at<VH, typename Mem::Elem, P>(src, c, off); };
+        auto theta = [&](Off off) { return theta_at<VH, typename Mem::Elem, P>(src, c, off); };
         const float th1 = theta(own);
         if (oxm) {
             const float tw = c.a1[0] * th1 + c.a2[0] * theta(rC + mem.col(x, 1)) + c.a3[0];
@@ -168,11 +173,11 @@ __device__ __forceinline__ void gather_mem(const Mem& mem, const LatticeConst& c
 }
 
 // Gather from the stored buffer.
-template <typename S, bool VH = false>
+template <typename S, bool VH = false, typename O = size_t>
 __device__ __forceinline__ void gather_node(const S* __restrict__ src, const LatticeConst& c, int x,
                                             int y, float a[9], float b[5])
 {
-    gather_mem<VH>(global_mem(src, c), c, x, y, a, b);
+    gather_mem<VH>(global_mem<O>(src, c), c, x, y, a, b);
 }
 
 // Round the post-collision state of one node (x, y) into the storage type: the
@@ -199,15 +204,15 @@ __device__ __forceinline__ void round_node(const typename Wide<S>::type fa[9],
     for (int i = 0; i < 5; ++i) out[9 + i] = sr_round(tb[i], h + (unsigned)(9 + i) * 0x9E3779B9u);
 }
 
-// Store the post-collision state of node (x, y), nontemporal.
-template <typename S>
+// Store the post-collision state of node (x, y), nontemporal; O as in GlobalMem.
+template <typename S, typename O = size_t>
 __device__ __forceinline__ void store_node(S* __restrict__ dst, const LatticeConst& c, int x, int y,
                                            const typename Wide<S>::type fa[9],
                                            const typename Wide<S>::type tb[5])
 {
     S v[14];
     round_node<S>(fa, tb, v, x, y);
-    const unsigned own = node_off(c, x, y);
+    const O own = (O)node_off(c, x, y);
 #pragma unroll
     for (int i = 0; i < 14; ++i) st_nt(dst + i * kBlock + own, v[i]);
 }
@@ -296,7 +301,7 @@ __device__ __forceinline__ int tile_of_block(int total, int remap)
     return (b & 7) * per + (b >> 3);
 }
 
-template <typename S, int ROWS, bool VH>
+template <typename S, int ROWS, bool VH, typename O>
 __global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __restrict__ dst,
                                                const LatticeConst c, int tiles_x, int tiles_total,
                                                int remap)
@@ -334,10 +339,10 @@ __global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __r
         if (y < c.ny) {
             float a[9], b[5];
             W fa[9], tb[5];
-            gather_node<S, VH>(src, c, x, y, a, b);
+            gather_node<S, VH, O>(src, c, x, y, a, b);
             NodeMacro m;
             collide<W, VH>(c, a, b, fa, tb, m);
-            store_node(dst, c, x, y, fa, tb);
+            store_node<S, O>(dst, c, x, y, fa, tb);
         }
     }
 }
@@ -362,6 +367,7 @@ struct Tile2 {
 template <typename S, int TY>
 struct TileMem {
     typedef S Elem;
+    typedef unsigned Off;
     const S* p;
     int x0, y0;
     static constexpr unsigned P = Tile2<TY>::P;
@@ -387,7 +393,7 @@ __device__ __forceinline__ bool tile_interior(const LatticeConst& c, int X0, int
 // (X0 - 1 + lx, Y0 - 1 + ly) of the tile with its ring, advanced from the stored buffer
 // into LDS. In a periodic direction a ring node outside the lattice is the wrapped
 // node; in a walled one it does not exist and its LDS entry is never read.
-template <typename S, bool VH, int TY, int NT>
+template <typename S, bool VH, int TY, int NT, typename O>
 __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const LatticeConst& c, S* tile,
                                              int X0, int Y0, int tid)
 {
@@ -417,7 +423,7 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
             gy = wrap_index(gy, c.ny);
         }
         float a[9], b[5];
-        gather_node<S, VH>(src, c, gx, gy, a, b);
+        gather_node<S, VH, O>(src, c, gx, gy, a, b);
         finish(a, b, gx, gy, lx, ly);
     };
     // one wave per row for the kBlock interior columns, then the two ring columns
@@ -445,7 +451,7 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
 }
 
 // Phase 2 for thread tid: the tile's own nodes advanced from LDS and stored.
-template <typename S, bool VH, int TY, int NT>
+template <typename S, bool VH, int TY, int NT, typename O>
 __device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeConst& c, const S* tile,
                                              int X0, int Y0, int tid)
 {
@@ -484,12 +490,12 @@ __device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeC
             NodeMacro m;
             gather_mem<VH>(mem, c, gx, gy, a, b);
             collide<W, VH>(c, a, b, fa, tb, m);
-            store_node(dst, c, gx, gy, fa, tb);
+            store_node<S, O>(dst, c, gx, gy, fa, tb);
         }
     }
 }
 
-template <typename S, bool VH, int TY, int NT>
+template <typename S, bool VH, int TY, int NT, typename O>
 __global__ void __launch_bounds__(NT) k_step2(const S* __restrict__ src, S* __restrict__ dst,
                                               const LatticeConst c, int tiles_x, int tiles_total,
                                               int remap)
@@ -502,8 +508,8 @@ __global__ void __launch_bounds__(NT) k_step2(const S* __restrict__ src, S* __re
     if (t >= tiles_total) return;
     const int X0 = (t % tiles_x) * (int)kBlock;
     const int Y0 = (t / tiles_x) * TY;
-    step2_phase1<S, VH, TY, NT>(src, c, tile, X0, Y0, (int)threadIdx.x);
+    step2_phase1<S, VH, TY, NT, O>(src, c, tile, X0, Y0, (int)threadIdx.x);
     __syncthreads();
-    step2_phase2<S, VH, TY, NT>(dst, c, tile, X0, Y0, (int)threadIdx.x);
+    step2_phase2<S, VH, TY, NT, O>(dst, c, tile, X0, Y0, (int)threadIdx.x);
 }
 }  // namespace clbm

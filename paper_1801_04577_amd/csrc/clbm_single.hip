@@ -55,6 +55,12 @@ size_t row_elems(int nx) { return ((size_t)nx + kBlock - 1) / kBlock * kBlockEle
 
 size_t buffer_elems(int nx, int ny) { return row_elems(nx) * (size_t)ny; }
 
+dim3 node_grid(const LatticeConst& c, dim3 blk)
+{
+    const size_t nb = (size_t)((c.nx + blk.x - 1) / blk.x) * ((c.ny + blk.y - 1) / blk.y);
+    return dim3((unsigned)nb, 1, 1);
+}
+
 clbm_status validate(const clbm_params* p, Rates* r)
 {
     if (!p) return CLBM_ERR_INVALID_ARG;
@@ -79,9 +85,13 @@ clbm_status validate(const clbm_params* p, Rates* r)
     // Eq. (27) needs a second layer of nodes next to each wall.
     if (p->side[0].kind == CLBM_WALL && p->nx < 2) return CLBM_ERR_INVALID_ARG;
     if (p->side[2].kind == CLBM_WALL && p->ny < 2) return CLBM_ERR_INVALID_ARG;
-    // 32-bit element offsets inside one population buffer.
-    const double elems = (double)buffer_elems(p->nx, p->ny);
-    if (elems >= 4294967295.0) return CLBM_ERR_UNSUPPORTED;
+    // Offsets within one row of a population buffer are 32-bit byte offsets (rows are
+    // addressed with 64-bit offsets, so the lattice size is bounded by memory only).
+    if ((double)row_elems(p->nx) * sizeof(float) >= 4294967295.0) return CLBM_ERR_UNSUPPORTED;
+    // The per-node kernels (initialisation, exports) launch one work-item per node, in
+    // blocks of 64 x 4 nodes, and a launch holds fewer than 2^32 work-items.
+    if ((double)((p->nx + 63) / 64) * 64.0 * (double)((p->ny + 3) / 4) * 4.0 >= 4294967295.0)
+        return CLBM_ERR_UNSUPPORTED;
     Rates tmp;
     Rates* rr = r ? r : &tmp;
     clbm_status st = derive_rates(p, rr);
@@ -178,27 +188,33 @@ struct StepLaunch {
     int tiles_x, tiles_total, remap;
 };
 
-template <typename S, bool VH>
+template <typename S, bool VH, typename O>
 static const void* step_fn(int rows)
 {
     switch (rows) {
-        case 2: return reinterpret_cast<const void*>(&k_step<S, 2, VH>);
-        case 4: return reinterpret_cast<const void*>(&k_step<S, 4, VH>);
-        default: return reinterpret_cast<const void*>(&k_step<S, 1, VH>);
+        case 2: return reinterpret_cast<const void*>(&k_step<S, 2, VH, O>);
+        case 4: return reinterpret_cast<const void*>(&k_step<S, 4, VH, O>);
+        default: return reinterpret_cast<const void*>(&k_step<S, 1, VH, O>);
     }
 }
 
+// Element offsets in the step kernels: 32-bit unless a population buffer holds 2^32
+// elements or more.
+static bool wide_offsets(const LatticeConst& c) { return (size_t)c.rowlen * c.ny >= 0xFFFFFFFFull; }
+
 template <typename S>
-static const void* step_fn(int rows, bool viscous)
+static const void* step_fn(int rows, bool viscous, bool wide)
 {
-    return viscous ? step_fn<S, true>(rows) : step_fn<S, false>(rows);
+    if (wide) return viscous ? step_fn<S, true, size_t>(rows) : step_fn<S, false, size_t>(rows);
+    return viscous ? step_fn<S, true, unsigned>(rows) : step_fn<S, false, unsigned>(rows);
 }
 
 static StepLaunch plan_step(const LatticeConst& c, int precision, const clbm_launch& L)
 {
     StepLaunch s;
-    s.fn = precision == CLBM_FP16_SHIFTED ? step_fn<__half>(L.rows_per_thread, c.viscous != 0)
-                                          : step_fn<float>(L.rows_per_thread, c.viscous != 0);
+    const bool wide = wide_offsets(c);
+    s.fn = precision == CLBM_FP16_SHIFTED ? step_fn<__half>(L.rows_per_thread, c.viscous != 0, wide)
+                                          : step_fn<float>(L.rows_per_thread, c.viscous != 0, wide);
     s.block = dim3(L.block_x, L.block_y, 1);
     s.tiles_x = (c.nx + L.block_x - 1) / L.block_x;
     const int rows_per_tile = L.block_y * L.rows_per_thread;
@@ -249,10 +265,13 @@ struct Step2Launch {
 };
 
 template <typename S, int TY, int NT>
-static const void* step2_fn(bool viscous)
+static const void* step2_fn(bool viscous, bool wide)
 {
-    return viscous ? reinterpret_cast<const void*>(&k_step2<S, true, TY, NT>)
-                   : reinterpret_cast<const void*>(&k_step2<S, false, TY, NT>);
+    if (wide)
+        return viscous ? reinterpret_cast<const void*>(&k_step2<S, true, TY, NT, size_t>)
+                       : reinterpret_cast<const void*>(&k_step2<S, false, TY, NT, size_t>);
+    return viscous ? reinterpret_cast<const void*>(&k_step2<S, true, TY, NT, unsigned>)
+                   : reinterpret_cast<const void*>(&k_step2<S, false, TY, NT, unsigned>);
 }
 
 static Step2Launch plan_step2(const LatticeConst& c, int precision, const clbm_launch& L)
@@ -260,8 +279,8 @@ static Step2Launch plan_step2(const LatticeConst& c, int precision, const clbm_l
     Step2Launch s;
     const bool f16 = precision == CLBM_FP16_SHIFTED;
     const int rows = f16 ? kTwoStepRowsF16 : kTwoStepRows;
-    s.fn = f16 ? step2_fn<__half, kTwoStepRowsF16, kTwoStepThreadsF16>(c.viscous != 0)
-               : step2_fn<float, kTwoStepRows, kTwoStepThreads>(c.viscous != 0);
+    s.fn = f16 ? step2_fn<__half, kTwoStepRowsF16, kTwoStepThreadsF16>(c.viscous != 0, wide_offsets(c))
+               : step2_fn<float, kTwoStepRows, kTwoStepThreads>(c.viscous != 0, wide_offsets(c));
     s.tiles_x = (c.nx + (int)kBlock - 1) / (int)kBlock;
     const int tiles_y = (c.ny + rows - 1) / rows;
     s.tiles_total = s.tiles_x * tiles_y;
@@ -432,11 +451,6 @@ clbm_status build_graph(clbm_handle* h, int start)
     h->graph[start] = g;
     h->gexec[start] = ex;
     return CLBM_OK;
-}
-
-dim3 node_grid(const LatticeConst& c, dim3 blk)
-{
-    return dim3((c.nx + blk.x - 1) / blk.x, (c.ny + blk.y - 1) / blk.y, 1);
 }
 
 }  // namespace

@@ -107,3 +107,28 @@ def test_create_rejects_small_workspace(L):
     assert st == -3 and not h.value
     st = L.clbm_create(ctypes.byref(p), ctypes.c_void_p(258), 1 << 30, None, ctypes.byref(h))
     assert st == -1                                       # misaligned workspace
+
+
+def test_size_limits(L):
+    """Lattices are bounded by device memory, not by 32-bit element offsets: a 4096 x
+    76000 lattice (population buffers of 4.36e9 elements) is accepted, with 112 B per node
+    for the two FP32 buffers. Rejected (CLBM_ERR_UNSUPPORTED): a row of 2^32 bytes or
+    more, 2^32 or more nodes after padding to 64 x 4 blocks, and a batched instance whose
+    buffer holds 2^32 elements or more."""
+    size = ctypes.c_size_t()
+
+    def status(nx, ny):
+        q = clbm.make_params(W.cavity(64))
+        q.nx, q.ny = nx, ny
+        return L.clbm_workspace_bytes(ctypes.byref(q), ctypes.byref(size))
+
+    assert status(4096, 76000) == 0
+    assert size.value >= 112 * 4096 * 76000
+    assert status(77_000_000, 2) == -6
+    assert status(65536, 65536) == -6
+    assert status(65536, 65532) == 0
+    q = clbm.make_params(W.cavity(64))
+    q.nx, q.ny = 4096, 76000
+    assert L.clbm_batch_workspace_bytes(1, ctypes.byref(q), ctypes.byref(size)) == -6
+    q.ny = 74000
+    assert L.clbm_batch_workspace_bytes(1, ctypes.byref(q), ctypes.byref(size)) == 0

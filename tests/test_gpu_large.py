@@ -108,3 +108,65 @@ def test_full_size_sampled_nodes_after_500_steps(precision):
     print("4096^2 sampled nodes after 500 steps (%s): worst error / bound = %.3f"
           % ("fp32" if precision == 0 else "fp16s", worst), flush=True)
     assert worst <= 1.0
+
+
+def _strip_errors(o, rows, gpu):
+    """Errors of GPU macroscopic rows (gpu: rho, ux, uy, T arrays) against rows of the
+    oracle's strip, in the metric of field_errors."""
+    ro, uxo, uyo, To = [a[rows] for a in o.macros()]
+    rg, uxg, uyg, Tg = gpu
+    umax = float(np.sqrt(uxo ** 2 + uyo ** 2).max())
+    du = float(np.sqrt((uxg - uxo) ** 2 + (uyg - uyo) ** 2).max())
+    return {"u": du / umax, "T": float(np.abs(Tg - To).max() / np.abs(To).max()),
+            "rho_abs": float(np.abs(rg - ro).max())}
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-5), (1, 1e-2)])
+def test_lattice_beyond_32bit_offsets(precision, tol):
+    """A 4096 x 76000 lattice: each population buffer holds 14 x 4096 x 76000 = 4.36e9
+    elements, so the rows above y = 74898 lie beyond 2^32 elements from the buffer
+    start. Walls on all four sides (Dirichlet x walls, a moving Robin top wall, an
+    adiabatic bottom wall), buoyancy, a heat source and seeded noise in u and T; one
+    launch of the default two-step kernel. After two steps a node depends only on nodes
+    within two rows, so the oracle advances the 16 top and 16 bottom rows of the lattice
+    as strips of 18 rows (the two extra rows end at a wall of their own, which affects
+    only those two rows) and every node of the 32 rows is compared."""
+    import torch
+    nx, ny, H = 4096, 76000, 16
+    sides = [W.dirichlet(0.4), W.dirichlet(-0.3), W.adiabatic(), W.robin(1.0, 0.5, 0.05, u_wall=0.04)]
+    kw = dict(g_beta=1e-4, Q=5e-6, Fx=2e-6)
+    prob = W.problem(nx, ny, 0.06, 0.08, sides, **kw)
+    seeds, amps = (101, 102, 103), (0.02, 0.02, 0.2)
+
+    def rows(y0, y1):
+        return [f32(W.noise_rows(sd, nx, y0, y1, a)) for sd, a in zip(seeds, amps)]
+
+    import paper_1801_04577_amd as clbm
+    dev = torch.device("cuda")
+    fields = [torch.empty(ny, nx, dtype=torch.float32, device=dev) for _ in range(3)]
+    chunk = 8192
+    for y0 in range(0, ny, chunk):
+        y1 = min(ny, y0 + chunk)
+        for t, a in zip(fields, rows(y0, y1)):
+            t[y0:y1].copy_(torch.from_numpy(a))
+    s = clbm.Solver(prob, precision)
+    s.init(ux=fields[0], uy=fields[1], T=fields[2])
+    s.step(2)
+    del fields
+    m = s.macros()
+    top = [t[ny - H:].cpu().numpy().astype(np.float64) for t in m]
+    bot = [t[:H].cpu().numpy().astype(np.float64) for t in m]
+    del m, s
+    torch.cuda.empty_cache()
+
+    wall = W.adiabatic()
+    o_top = run_oracle(W.problem(nx, H + 2, 0.06, 0.08, sides[:2] + [wall, sides[3]], **kw), 2,
+                       dict(zip(("ux", "uy", "T"), rows(ny - H - 2, ny))))
+    o_bot = run_oracle(W.problem(nx, H + 2, 0.06, 0.08, sides[:3] + [wall], **kw), 2,
+                       dict(zip(("ux", "uy", "T"), rows(0, H + 2))))
+    e_top = _strip_errors(o_top, slice(2, H + 2), top)
+    e_bot = _strip_errors(o_bot, slice(0, H), bot)
+    print("4096 x 76000 (%s), 2 steps: top rows %s, bottom rows %s"
+          % ("fp32" if precision == 0 else "fp16s", e_top, e_bot), flush=True)
+    for e in (e_top, e_bot):
+        assert e["u"] <= tol and e["T"] <= tol

@@ -77,8 +77,18 @@ def uniform01(seed, n):
 
 def noise_field(seed, nx, ny, amplitude):
     """amplitude * U(-1, 1) per node, [ny][nx] row-major, node index y*nx + x."""
-    u = uniform01(seed, nx * ny).reshape(ny, nx)
-    return amplitude * (2.0 * u - 1.0)
+    return noise_rows(seed, nx, 0, ny, amplitude)
+
+
+def noise_rows(seed, nx, y0, y1, amplitude):
+    """Rows y0..y1-1 of noise_field(seed, nx, ny, amplitude) for any ny >= y1 (the
+    counter of node (x, y) is y*nx + x, so a strip is generated on its own)."""
+    with np.errstate(over="ignore"):
+        ctr = ((np.uint64(seed) << np.uint64(32)) + np.uint64(y0 * nx)
+               + np.arange((y1 - y0) * nx, dtype=np.uint64))
+    z = splitmix64(ctr)
+    u = (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return amplitude * (2.0 * u.reshape(y1 - y0, nx) - 1.0)
 
 
 # --------------------------------------------------------------------------
