@@ -126,11 +126,12 @@ def test_lattice_beyond_32bit_offsets(precision, tol):
     """A 4096 x 76000 lattice: each population buffer holds 14 x 4096 x 76000 = 4.36e9
     elements, so the rows above y = 74898 lie beyond 2^32 elements from the buffer
     start. Walls on all four sides (Dirichlet x walls, a moving Robin top wall, an
-    adiabatic bottom wall), buoyancy, a heat source and seeded noise in u and T; one
-    launch of the default two-step kernel. After two steps a node depends only on nodes
-    within two rows, so the oracle advances the 16 top and 16 bottom rows of the lattice
-    as strips of 18 rows (the two extra rows end at a wall of their own, which affects
-    only those two rows) and every node of the 32 rows is compared."""
+    adiabatic bottom wall), buoyancy, a heat source and seeded noise in u and T; three
+    steps in the default launch (one two-step launch, then one single step), so both
+    step kernels run with 64-bit offsets. After three steps a node depends only on nodes
+    within three rows, so the oracle advances the 16 top and 16 bottom rows of the
+    lattice as strips of 19 rows (the three extra rows end at a wall of their own, which
+    affects only those rows) and every node of the 32 rows is compared."""
     import torch
     nx, ny, H = 4096, 76000, 16
     sides = [W.dirichlet(0.4), W.dirichlet(-0.3), W.adiabatic(), W.robin(1.0, 0.5, 0.05, u_wall=0.04)]
@@ -151,7 +152,7 @@ def test_lattice_beyond_32bit_offsets(precision, tol):
             t[y0:y1].copy_(torch.from_numpy(a))
     s = clbm.Solver(prob, precision)
     s.init(ux=fields[0], uy=fields[1], T=fields[2])
-    s.step(2)
+    s.step(3)
     del fields
     m = s.macros()
     top = [t[ny - H:].cpu().numpy().astype(np.float64) for t in m]
@@ -160,13 +161,13 @@ def test_lattice_beyond_32bit_offsets(precision, tol):
     torch.cuda.empty_cache()
 
     wall = W.adiabatic()
-    o_top = run_oracle(W.problem(nx, H + 2, 0.06, 0.08, sides[:2] + [wall, sides[3]], **kw), 2,
-                       dict(zip(("ux", "uy", "T"), rows(ny - H - 2, ny))))
-    o_bot = run_oracle(W.problem(nx, H + 2, 0.06, 0.08, sides[:3] + [wall], **kw), 2,
-                       dict(zip(("ux", "uy", "T"), rows(0, H + 2))))
-    e_top = _strip_errors(o_top, slice(2, H + 2), top)
+    o_top = run_oracle(W.problem(nx, H + 3, 0.06, 0.08, sides[:2] + [wall, sides[3]], **kw), 3,
+                       dict(zip(("ux", "uy", "T"), rows(ny - H - 3, ny))))
+    o_bot = run_oracle(W.problem(nx, H + 3, 0.06, 0.08, sides[:3] + [wall], **kw), 3,
+                       dict(zip(("ux", "uy", "T"), rows(0, H + 3))))
+    e_top = _strip_errors(o_top, slice(3, H + 3), top)
     e_bot = _strip_errors(o_bot, slice(0, H), bot)
-    print("4096 x 76000 (%s), 2 steps: top rows %s, bottom rows %s"
+    print("4096 x 76000 (%s), 3 steps: top rows %s, bottom rows %s"
           % ("fp32" if precision == 0 else "fp16s", e_top, e_bot), flush=True)
     for e in (e_top, e_bot):
         assert e["u"] <= tol and e["T"] <= tol
