@@ -21,7 +21,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIBPATH = os.path.join(_HERE, "liboracle.so")
+# CLBM_ORACLE_LIB names another build of the same source (the mutation tests load
+# copies with a planted mistake); the default is the library next to this file.
+_LIBPATH = os.environ.get("CLBM_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
@@ -186,6 +188,10 @@ def collide(prob, f, g):
 
 
 def default_threads():
+    """OMP_NUM_THREADS when set, else the host's cores (at most 16)."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
     return max(1, min(16, os.cpu_count() or 1))
 
 

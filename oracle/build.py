@@ -13,16 +13,17 @@ LIB = os.path.join(HERE, "liboracle.so")
 SOURCES = ["clbm_oracle.c", "net_oracle.c"]
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
-    tmp = LIB + ".tmp%d" % os.getpid()
+def build(verbose: bool = False, src_dir: str = HERE, out: str = LIB) -> str:
+    """Compile the sources found in src_dir (default: this directory) into out."""
+    srcs = [os.path.join(src_dir, s) for s in SOURCES if os.path.exists(os.path.join(src_dir, s))]
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
            "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp] + srcs + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
