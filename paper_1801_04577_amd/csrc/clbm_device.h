@@ -132,7 +132,10 @@ __device__ __forceinline__ float sr_round(double x, unsigned r)
 __device__ __forceinline__ __half sr_round(float x, unsigned r)
 {
     typedef _Float16 half2v __attribute__((ext_vector_type(2)));
-    const half2v v = __builtin_amdgcn_cvt_sr_f16_f32(half2v{0, 0}, x, r, false);
+    // The conversion writes the low half of its destination and keeps the high half; the
+    // destination starts as the bits of x (dead after this), so it needs no cleared
+    // register of its own. The high half is not used.
+    const half2v v = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(half2v, x), x, r, false);
     __half_raw raw;
     raw.data = v[0];
     return raw;
