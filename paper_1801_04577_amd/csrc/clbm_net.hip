@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <vector>
 
@@ -469,71 +470,121 @@ __global__ void k_pack_input(const float* __restrict__ xin, int Cin, int HW, int
     x[k] = f2bf(c < Cin ? xin[((size_t)b * Cin + c) * HW + r] : 0.f);
 }
 
+// Elementwise kernels over NHWC channel views. Each thread handles V consecutive
+// channels of one pixel: V = 8 (one 16-byte access) where the channel counts, strides
+// and offsets are multiples of 8, else V = 1. The arithmetic per channel is the same.
+template <int V>
+__device__ __forceinline__ void load_v(const bf16* p, float (&out)[V])
+{
+    if constexpr (V == 8) {
+        const bf16x8 t = *reinterpret_cast<const bf16x8*>(p);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) out[i] = bf2f(t[i]);
+    } else {
+        out[0] = bf2f(p[0]);
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void store_v(bf16* p, const float (&in)[V])
+{
+    if constexpr (V == 8) {
+        bf16x8 t;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) t[i] = f2bf(in[i]);
+        *reinterpret_cast<bf16x8*>(p) = t;
+    } else {
+        p[0] = f2bf(in[0]);
+    }
+}
+
 // 2x2 average pooling and nearest 2x upsampling on channel views.
+template <int V>
 __global__ void k_avgpool(const bf16* __restrict__ x, int xC, int xoff, int C, int H, int W,
                           int B, bf16* __restrict__ y, int yC, int yoff)
 {
-    const int Ho = H / 2, Wo = W / 2;
+    const int Ho = H / 2, Wo = W / 2, CV = C / V;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= B * Ho * Wo * C) return;
-    const int c = k % C, p = k / C;
+    if (k >= B * Ho * Wo * CV) return;
+    const int c = (k % CV) * V, p = k / CV;
     const int b = p / (Ho * Wo), r = p - b * Ho * Wo, oy = r / Wo, ox = r - oy * Wo;
     const size_t base = (size_t)b * H * W;
-    const float s = bf2f(x[(base + (2 * oy) * W + 2 * ox) * xC + xoff + c]) +
-                    bf2f(x[(base + (2 * oy) * W + 2 * ox + 1) * xC + xoff + c]) +
-                    bf2f(x[(base + (2 * oy + 1) * W + 2 * ox) * xC + xoff + c]) +
-                    bf2f(x[(base + (2 * oy + 1) * W + 2 * ox + 1) * xC + xoff + c]);
-    y[(size_t)p * yC + yoff + c] = f2bf(0.25f * s);
+    float v00[V], v01[V], v10[V], v11[V], out[V];
+    load_v<V>(x + (base + (2 * oy) * W + 2 * ox) * xC + xoff + c, v00);
+    load_v<V>(x + (base + (2 * oy) * W + 2 * ox + 1) * xC + xoff + c, v01);
+    load_v<V>(x + (base + (2 * oy + 1) * W + 2 * ox) * xC + xoff + c, v10);
+    load_v<V>(x + (base + (2 * oy + 1) * W + 2 * ox + 1) * xC + xoff + c, v11);
+#pragma unroll
+    for (int i = 0; i < V; ++i) out[i] = 0.25f * (v00[i] + v01[i] + v10[i] + v11[i]);
+    store_v<V>(y + (size_t)p * yC + yoff + c, out);
 }
 
+template <int V>
 __global__ void k_upsample(const bf16* __restrict__ x, int xC, int xoff, int C, int H, int W, int B,
                            bf16* __restrict__ y, int yC, int yoff)
 {
     // x is H x W, y is 2H x 2W
-    const int Ho = 2 * H, Wo = 2 * W;
+    const int Ho = 2 * H, Wo = 2 * W, CV = C / V;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= B * Ho * Wo * C) return;
-    const int c = k % C, p = k / C;
+    if (k >= B * Ho * Wo * CV) return;
+    const int c = (k % CV) * V, p = k / CV;
     const int b = p / (Ho * Wo), r = p - b * Ho * Wo, oy = r / Wo, ox = r - oy * Wo;
-    y[(size_t)p * yC + yoff + c] = x[((size_t)b * H * W + (oy / 2) * W + ox / 2) * xC + xoff + c];
+    const bf16* src = x + ((size_t)b * H * W + (oy / 2) * W + ox / 2) * xC + xoff + c;
+    bf16* dst = y + (size_t)p * yC + yoff + c;
+    if constexpr (V == 8) *reinterpret_cast<bf16x8*>(dst) = *reinterpret_cast<const bf16x8*>(src);
+    else dst[0] = src[0];
 }
 
 // Gradient of the nearest upsampling: 2x2 sums (dy is 2H x 2W, dx is H x W).
+template <int V>
 __global__ void k_upsample_bwd(const bf16* __restrict__ dy, int dyC, int dyoff, int C, int H, int W,
                                int B, bf16* __restrict__ dx, int dxC, int dxoff)
 {
-    const int Wi = 2 * W;
+    const int Wi = 2 * W, CV = C / V;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= B * H * W * C) return;
-    const int c = k % C, p = k / C;
+    if (k >= B * H * W * CV) return;
+    const int c = (k % CV) * V, p = k / CV;
     const int b = p / (H * W), r = p - b * H * W, oy = r / W, ox = r - oy * W;
     const size_t base = (size_t)b * 4 * H * W;
-    const float s = bf2f(dy[(base + (2 * oy) * Wi + 2 * ox) * dyC + dyoff + c]) +
-                    bf2f(dy[(base + (2 * oy) * Wi + 2 * ox + 1) * dyC + dyoff + c]) +
-                    bf2f(dy[(base + (2 * oy + 1) * Wi + 2 * ox) * dyC + dyoff + c]) +
-                    bf2f(dy[(base + (2 * oy + 1) * Wi + 2 * ox + 1) * dyC + dyoff + c]);
-    dx[(size_t)p * dxC + dxoff + c] = f2bf(s);
+    float v00[V], v01[V], v10[V], v11[V], out[V];
+    load_v<V>(dy + (base + (2 * oy) * Wi + 2 * ox) * dyC + dyoff + c, v00);
+    load_v<V>(dy + (base + (2 * oy) * Wi + 2 * ox + 1) * dyC + dyoff + c, v01);
+    load_v<V>(dy + (base + (2 * oy + 1) * Wi + 2 * ox) * dyC + dyoff + c, v10);
+    load_v<V>(dy + (base + (2 * oy + 1) * Wi + 2 * ox + 1) * dyC + dyoff + c, v11);
+#pragma unroll
+    for (int i = 0; i < V; ++i) out[i] = v00[i] + v01[i] + v10[i] + v11[i];
+    store_v<V>(dx + (size_t)p * dxC + dxoff + c, out);
 }
 
 // dz = (dskip + pool_backward(dpool)) * (a > 0), all at H x W; dpool is H/2 x W/2.
 // With dskip == nullptr and dpool == nullptr it is the plain ReLU gradient dz = dy * (a > 0)
 // where dy is passed as dskip.
+template <int V>
 __global__ void k_relu_grad(const bf16* __restrict__ dskip, int sC, int soff,
                             const bf16* __restrict__ dpool, int pC, const bf16* __restrict__ a,
                             int aC, int aoff, int C, int H, int W, int B, bf16* __restrict__ dz,
                             int zC)
 {
+    const int CV = C / V;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= B * H * W * C) return;
-    const int c = k % C, p = k / C;
-    float g = dskip ? bf2f(dskip[(size_t)p * sC + soff + c]) : 0.f;
+    if (k >= B * H * W * CV) return;
+    const int c = (k % CV) * V, p = k / CV;
+    float g[V], av[V], out[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) g[i] = 0.f;
+    if (dskip) load_v<V>(dskip + (size_t)p * sC + soff + c, g);
     if (dpool) {
         const int b = p / (H * W), r = p - b * H * W, py = r / W, px = r - py * W;
         const int Wo = W / 2;
-        g += 0.25f * bf2f(dpool[((size_t)b * (H / 2) * Wo + (py / 2) * Wo + px / 2) * pC + c]);
+        float d[V];
+        load_v<V>(dpool + ((size_t)b * (H / 2) * Wo + (py / 2) * Wo + px / 2) * pC + c, d);
+#pragma unroll
+        for (int i = 0; i < V; ++i) g[i] += 0.25f * d[i];
     }
-    const float av = bf2f(a[(size_t)p * aC + aoff + c]);
-    dz[(size_t)p * zC + c] = f2bf(av > 0.f ? g : 0.f);
+    load_v<V>(a + (size_t)p * aC + aoff + c, av);
+#pragma unroll
+    for (int i = 0; i < V; ++i) out[i] = av[i] > 0.f ? g[i] : 0.f;
+    store_v<V>(dz + (size_t)p * zC + c, out);
 }
 
 // Mean squared error: dy = 2 (y - t)/n into a bf16 NHWC buffer (zero channel padding),
@@ -864,6 +915,28 @@ void layout_net(clbm_net* n, Alloc& a)
 
 dim3 grid1(size_t n, int block = 256) { return dim3((unsigned)((n + block - 1) / block)); }
 
+// True when every channel count, stride and offset allows 8-channel (16-byte) accesses.
+bool vec8(std::initializer_list<int> v)
+{
+    for (int x : v)
+        if (x % 8 != 0) return false;
+    return true;
+}
+
+// Gradient of the nearest upsampling into a channel view (dy: 2H x 2W, dx: H x W).
+clbm_status upsample_bwd(clbm_net* n, TView dy, int C, int H, int W, TView dx)
+{
+    const int B = n->d.batch;
+    if (vec8({C, dy.C, dy.off, dx.C, dx.off}))
+        hipLaunchKernelGGL(k_upsample_bwd<8>, grid1((size_t)B * H * W * (C / 8)), dim3(256), 0, n->stream,
+                           dy.p, dy.C, dy.off, C, H, W, B, dx.p, dx.C, dx.off);
+    else
+        hipLaunchKernelGGL(k_upsample_bwd<1>, grid1((size_t)B * H * W * C), dim3(256), 0, n->stream,
+                           dy.p, dy.C, dy.off, C, H, W, B, dx.p, dx.C, dx.off);
+    CLBM_HIP(hipGetLastError());
+    return CLBM_OK;
+}
+
 clbm_status conv_launch(clbm_net* n, const Layer& l, TView in, int cin_pad, const bf16* w,
                         const float* bias, int N, int nb, int npad, int mode, TView out, float* yf)
 {
@@ -914,16 +987,24 @@ clbm_status ew_launch_check() { CLBM_HIP(hipGetLastError()); return CLBM_OK; }
 clbm_status pool(clbm_net* n, TView x, int C, int H, int W, TView y)
 {
     const int B = n->d.batch;
-    hipLaunchKernelGGL(k_avgpool, grid1((size_t)B * (H / 2) * (W / 2) * C), dim3(256), 0, n->stream,
-                       x.p, x.C, x.off, C, H, W, B, y.p, y.C, y.off);
+    if (vec8({C, x.C, x.off, y.C, y.off}))
+        hipLaunchKernelGGL(k_avgpool<8>, grid1((size_t)B * (H / 2) * (W / 2) * (C / 8)), dim3(256), 0,
+                           n->stream, x.p, x.C, x.off, C, H, W, B, y.p, y.C, y.off);
+    else
+        hipLaunchKernelGGL(k_avgpool<1>, grid1((size_t)B * (H / 2) * (W / 2) * C), dim3(256), 0, n->stream,
+                           x.p, x.C, x.off, C, H, W, B, y.p, y.C, y.off);
     return ew_launch_check();
 }
 
 clbm_status upsample(clbm_net* n, TView x, int C, int H, int W, TView y)
 {
     const int B = n->d.batch;
-    hipLaunchKernelGGL(k_upsample, grid1((size_t)B * 4 * H * W * C), dim3(256), 0, n->stream, x.p,
-                       x.C, x.off, C, H, W, B, y.p, y.C, y.off);
+    if (vec8({C, x.C, x.off, y.C, y.off}))
+        hipLaunchKernelGGL(k_upsample<8>, grid1((size_t)B * 4 * H * W * (C / 8)), dim3(256), 0, n->stream,
+                           x.p, x.C, x.off, C, H, W, B, y.p, y.C, y.off);
+    else
+        hipLaunchKernelGGL(k_upsample<1>, grid1((size_t)B * 4 * H * W * C), dim3(256), 0, n->stream, x.p,
+                           x.C, x.off, C, H, W, B, y.p, y.C, y.off);
     return ew_launch_check();
 }
 
@@ -974,9 +1055,14 @@ clbm_status conv_backward(clbm_net* n, int k, TView dz)
 clbm_status relu_grad(clbm_net* n, TView dy, TView dpool_parent, TView act, int C, int H, int W, TView dz)
 {
     const int B = n->d.batch;
-    hipLaunchKernelGGL(k_relu_grad, grid1((size_t)B * H * W * C), dim3(256), 0, n->stream, dy.p, dy.C,
-                       dy.off, dpool_parent.p, dpool_parent.C, act.p, act.C, act.off, C, H, W, B,
-                       dz.p, dz.C);
+    if (vec8({C, dy.C, dy.off, dpool_parent.C, act.C, act.off, dz.C}))
+        hipLaunchKernelGGL(k_relu_grad<8>, grid1((size_t)B * H * W * (C / 8)), dim3(256), 0, n->stream,
+                           dy.p, dy.C, dy.off, dpool_parent.p, dpool_parent.C, act.p, act.C, act.off, C,
+                           H, W, B, dz.p, dz.C);
+    else
+        hipLaunchKernelGGL(k_relu_grad<1>, grid1((size_t)B * H * W * C), dim3(256), 0, n->stream, dy.p,
+                           dy.C, dy.off, dpool_parent.p, dpool_parent.C, act.p, act.C, act.off, C, H,
+                           W, B, dz.p, dz.C);
     return ew_launch_check();
 }
 
@@ -1133,25 +1219,19 @@ clbm_status clbm_net_backward(clbm_net* n, const float* d_target, double* loss)
     if ((st = relu_grad(n, V(n->g_d1a, w1, 0), none, V(n->d1a, w1, 0), w1, H, W, zv(w1)))) return st;
     if ((st = conv_backward(n, 12, zv(w1)))) return st;
     // g_cat1 = [d up(d2b) | d s1]
-    hipLaunchKernelGGL(k_upsample_bwd, grid1((size_t)B * (H / 2) * (W / 2) * w2), dim3(256), 0, n->stream,
-                       n->g_cat1, w2 + w1, 0, w2, H / 2, W / 2, B, n->g_d2b, w2, 0);
-    CLBM_HIP(hipGetLastError());
+    if ((st = upsample_bwd(n, V(n->g_cat1, w2 + w1, 0), w2, H / 2, W / 2, V(n->g_d2b, w2, 0)))) return st;
     // level-2 decoder
     if ((st = relu_grad(n, V(n->g_d2b, w2, 0), none, V(n->d2b, w2, 0), w2, H / 2, W / 2, zv(w2)))) return st;
     if ((st = conv_backward(n, 11, zv(w2)))) return st;
     if ((st = relu_grad(n, V(n->g_d2a, w2, 0), none, V(n->d2a, w2, 0), w2, H / 2, W / 2, zv(w2)))) return st;
     if ((st = conv_backward(n, 10, zv(w2)))) return st;
-    hipLaunchKernelGGL(k_upsample_bwd, grid1((size_t)B * (H / 4) * (W / 4) * w3), dim3(256), 0, n->stream,
-                       n->g_cat2, w3 + w2, 0, w3, H / 4, W / 4, B, n->g_d3b, w3, 0);
-    CLBM_HIP(hipGetLastError());
+    if ((st = upsample_bwd(n, V(n->g_cat2, w3 + w2, 0), w3, H / 4, W / 4, V(n->g_d3b, w3, 0)))) return st;
     // level-3 decoder
     if ((st = relu_grad(n, V(n->g_d3b, w3, 0), none, V(n->d3b, w3, 0), w3, H / 4, W / 4, zv(w3)))) return st;
     if ((st = conv_backward(n, 9, zv(w3)))) return st;
     if ((st = relu_grad(n, V(n->g_d3a, w3, 0), none, V(n->d3a, w3, 0), w3, H / 4, W / 4, zv(w3)))) return st;
     if ((st = conv_backward(n, 8, zv(w3)))) return st;
-    hipLaunchKernelGGL(k_upsample_bwd, grid1((size_t)B * (H / 8) * (W / 8) * w4), dim3(256), 0, n->stream,
-                       n->g_cat3, w4 + w3, 0, w4, H / 8, W / 8, B, n->g_m4, w4, 0);
-    CLBM_HIP(hipGetLastError());
+    if ((st = upsample_bwd(n, V(n->g_cat3, w4 + w3, 0), w4, H / 8, W / 8, V(n->g_m4, w4, 0)))) return st;
     // bottom level
     if ((st = relu_grad(n, V(n->g_m4, w4, 0), none, V(n->m4, w4, 0), w4, H / 8, W / 8, zv(w4)))) return st;
     if ((st = conv_backward(n, 7, zv(w4)))) return st;
