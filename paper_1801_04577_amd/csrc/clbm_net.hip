@@ -273,7 +273,7 @@ template <int NCO, int NCI>
 __global__ void __launch_bounds__(kWgThreads) k_wgrad(const bf16* __restrict__ dz, int zC, int Cout,
                                                       const bf16* __restrict__ x, int xC, int xoff, int Cin,
                                                       int H, int W, int P, int pix_per_split,
-                                                      float* __restrict__ part)
+                                                      float* __restrict__ part, float* __restrict__ bpart)
 {
     constexpr int CO = 16 * NCO, CI = 16 * NCI;
     __shared__ __attribute__((aligned(16))) bf16 sdz[CO * kWgLd];
@@ -285,6 +285,10 @@ __global__ void __launch_bounds__(kWgThreads) k_wgrad(const bf16* __restrict__ d
     const int HW = H * W;
     const int pbeg = split * pix_per_split, pend = min(P, pbeg + pix_per_split);
     const int r16 = lane & 15, k8 = (lane >> 4) * 8;
+    // The workgroups of the first input-channel block also sum dz over their pixels: the
+    // bias gradient's partial for this split (bpart[split][co]), from the staged dz.
+    const bool bias = bpart != nullptr && blockIdx.x % cib_n == 0;
+    float bsum = 0.f;
     f32x4 acc[3][NCO][NCI];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
@@ -329,6 +333,10 @@ __global__ void __launch_bounds__(kWgThreads) k_wgrad(const bf16* __restrict__ d
                     bf16_bits(v[0][c]) | (bf16_bits(v[1][c]) << 16);
         }
         __syncthreads();
+        if (bias && tid < CO) {
+#pragma unroll 8
+            for (int q = 0; q < kWgP; ++q) bsum += bf2f(sdz[tid * kWgLd + q]);
+        }
         bf16x8 a[NCO];
 #pragma unroll
         for (int i = 0; i < NCO; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&sdz[(16 * i + r16) * kWgLd + k8]);
@@ -356,6 +364,7 @@ __global__ void __launch_bounds__(kWgThreads) k_wgrad(const bf16* __restrict__ d
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
                     out[((size_t)(16 * i + v) * 9 + 3 * wave + d) * Cin + 16 * j] = acc[d][i][j][v];
+    if (bias && tid < CO) bpart[(size_t)split * Cout + co0 + tid] = bsum;
 }
 
 // Largest 16-channel block count in {4, 2, 1} that divides n16 (channels / 16).
@@ -374,9 +383,6 @@ inline int wgrad_pixels_per_split(size_t P, int cout16, int cin_pad)
     return (int)((pps + kWgP - 1) / kWgP * kWgP);
 }
 
-// Pixels per split of the bias gradient.
-constexpr int kBiasPixelsPerSplit = 256;
-
 // Sum of the split partials in split order, written in the canonical layout
 // grad[co][ci][ky][kx] for co < Cout_real, ci < Cin_real (the partials use the padded
 // strides Cout, Cin). Threads run along the partials' own layout [co][tap][ci], so
@@ -394,25 +400,6 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, int splits, int C
 #pragma unroll 8
     for (int sp = 0; sp < splits; ++sp) s += part[sp * plane + k];
     grad[((size_t)co * Cin_real + ci) * 9 + tap] = s;
-}
-
-// Bias gradient: db[c] = sum over pixels of dz[p][c]; block (64 channels x 4 rows),
-// one partial per block row of pixels, then a fixed-order sum over the splits.
-__global__ void __launch_bounds__(256) k_bias_grad(const bf16* __restrict__ dz, int zC, int C, int P,
-                                                   int pix_per_split, float* __restrict__ part)
-{
-    __shared__ float lds[4][64];
-    const int c = blockIdx.x * 64 + threadIdx.x;
-    const int split = blockIdx.y;
-    const int pbeg = split * pix_per_split, pend = min(P, pbeg + pix_per_split);
-    float s = 0.f;
-    if (c < C)
-        for (int p = pbeg + threadIdx.y; p < pend; p += 4) s += bf2f(dz[(size_t)p * zC + c]);
-    lds[threadIdx.y][threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.y == 0 && c < C)
-        part[(size_t)split * C + c] = (lds[0][threadIdx.x] + lds[1][threadIdx.x]) +
-                                      (lds[2][threadIdx.x] + lds[3][threadIdx.x]);
 }
 
 // Sum of the bias partials of channel blockIdx.x: each thread sums a fixed strided
@@ -869,7 +856,7 @@ void layout_net(clbm_net* n, Alloc& a)
         const int c16 = round_up(l.cout, 16);
         const size_t pps = (size_t)wgrad_pixels_per_split(P, c16, l.cin_pad);
         wp = std::max(wp, (P + pps - 1) / pps * c16 * 9 * l.cin_pad);
-        bp = std::max(bp, (P + kBiasPixelsPerSplit - 1) / kBiasPixelsPerSplit * l.cout);
+        bp = std::max(bp, (P + pps - 1) / pps * c16);
     }
     n->wpart_floats = wp;
     n->wpart = a.take<float>(wp);
@@ -1026,8 +1013,8 @@ clbm_status conv_backward(clbm_net* n, int k, TView dz)
                               : (nci == 4 ? (const void*)&k_wgrad<1, 4> : nci == 2 ? (const void*)&k_wgrad<1, 2> : (const void*)&k_wgrad<1, 1>);
     {
         const bf16* zp = dz.p; int zc = dz.C, co = cout16; const bf16* xp = l.in.p; int xc = l.in.C, xo = l.in.off;
-        int ci = l.cin_pad, h = l.H, w = l.W, pp = P, ps = pps; float* pt = n->wpart;
-        void* args[] = {&zp, &zc, &co, &xp, &xc, &xo, &ci, &h, &w, &pp, &ps, &pt};
+        int ci = l.cin_pad, h = l.H, w = l.W, pp = P, ps = pps; float* pt = n->wpart; float* bt = n->bpart;
+        void* args[] = {&zp, &zc, &co, &xp, &xc, &xo, &ci, &h, &w, &pp, &ps, &pt, &bt};
         CLBM_HIP(hipLaunchKernel(wg, dim3((cout16 / (16 * nco)) * (l.cin_pad / (16 * nci)), splits),
                                  dim3(kWgThreads), args, 0, n->stream));
     }
@@ -1035,12 +1022,8 @@ clbm_status conv_backward(clbm_net* n, int k, TView dz)
     hipLaunchKernelGGL(k_wgrad_reduce, grid1((size_t)cout16 * 9 * l.cin_pad), dim3(256), 0, n->stream,
                        n->wpart, splits, cout16, l.cin_pad, l.cout, l.cin, n->grads + l.woff);
     CLBM_HIP(hipGetLastError());
-    // bias gradient
-    const int bsplits = (P + kBiasPixelsPerSplit - 1) / kBiasPixelsPerSplit;
-    hipLaunchKernelGGL(k_bias_grad, dim3((l.cout + 63) / 64, bsplits), dim3(64, 4), 0, n->stream, dz.p,
-                       dz.C, l.cout, P, kBiasPixelsPerSplit, n->bpart);
-    CLBM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_bias_reduce, dim3(l.cout), dim3(256), 0, n->stream, n->bpart, bsplits, l.cout,
+    // bias gradient: the weight-gradient kernel left one partial per split
+    hipLaunchKernelGGL(k_bias_reduce, dim3(l.cout), dim3(256), 0, n->stream, n->bpart, splits, cout16,
                        n->grads + l.boff);
     CLBM_HIP(hipGetLastError());
     // input gradient: convolution of dz with the flipped, transposed kernel
