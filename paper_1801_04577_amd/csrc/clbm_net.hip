@@ -297,6 +297,9 @@ __global__ void __launch_bounds__(kWgThreads) k_wgrad(const bf16* __restrict__ d
 #pragma unroll
             for (int j = 0; j < NCI; ++j) acc[d][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero = {};
+    // image, row and column of the chunk's first pixel, advanced with the chunk (no
+    // division per staged pixel)
+    int cb = pbeg / HW, cy = (pbeg - cb * HW) / W, cx = pbeg - cb * HW - cy * W;
     for (int pk = pbeg; pk < pend; pk += kWgP) {
         // stage dz: 16 pixel pairs x (2 NCO) channel octets
         for (int t = tid; t < 16 * 2 * NCO; t += kWgThreads) {
@@ -321,7 +324,14 @@ __global__ void __launch_bounds__(kWgThreads) k_wgrad(const bf16* __restrict__ d
             for (int h = 0; h < 2; ++h) {
                 const int p = pk + 2 * pair + h;
                 if (p < pend) {
-                    const int b = p / HW, rem = p - b * HW, py = rem / W, px = rem - py * W;
+                    int b = cb, py = cy, px = cx + 2 * pair + h;
+                    while (px >= W) {
+                        px -= W;
+                        if (++py == H) {
+                            py = 0;
+                            ++b;
+                        }
+                    }
                     const int sy = py + tap / 3 - 1, sx2 = px + tap % 3 - 1;
                     if (sy >= 0 && sy < H && sx2 >= 0 && sx2 < W)
                         v[h] = *reinterpret_cast<const bf16x8*>(x + (size_t)(b * HW + sy * W + sx2) * xC + xoff + ci);
@@ -352,6 +362,14 @@ __global__ void __launch_bounds__(kWgThreads) k_wgrad(const bf16* __restrict__ d
             }
         }
         __syncthreads();  // the next chunk overwrites the tiles
+        cx += kWgP;
+        while (cx >= W) {
+            cx -= W;
+            if (++cy == H) {
+                cy = 0;
+                ++cb;
+            }
+        }
     }
     // row of the result = output channel co0 + 16 i + 4 (lane / 16) + v, column = ci
     float* out = part + (size_t)split * Cout * 9 * Cin + (size_t)(co0 + 4 * (lane >> 4)) * 9 * Cin + ci0 + r16;
