@@ -113,6 +113,72 @@ def measured_traffic(precision, n, steps_per_launch):
     return prof.get("traffic_bytes_per_launch")
 
 
+VALU_PEAK_G_PER_S = 256 * 2.4  # wave-instructions per ns: one per clock per CU, 256 CUs at 2.4 GHz
+
+
+def summarize_valu(db, precision, n, command):
+    """Write the VALU issue and shader-clock summary of the step kernel under profiles/ from
+    one rocprofv3 run with --kernel-trace and the counters GRBM_GUI_ACTIVE,
+    SQ_ACTIVE_INST_VALU, SQ_BUSY_CU_CYCLES and SQ_INSTS_VALU."""
+    import sqlite3
+    import statistics
+    con = sqlite3.connect(db)
+    try:
+        per = {}
+        for k, c, v in con.execute("select kernel_name, counter_name, value from counters_collection"):
+            per.setdefault((k.split("(")[0].replace("void ", ""), c), []).append(v)
+        kname = sorted({k for k, _ in per if "k_step" in k}, key=lambda k: "k_step2" not in k)[0]
+        dur_us = [float(a) for nm, a in con.execute("select name, average from top_kernels")
+                  if nm.split("(")[0].replace("void ", "") == kname][0]
+    finally:
+        con.close()
+    m = {c: statistics.mean(v) for (k, c), v in per.items() if k == kname}
+    cycles = m["GRBM_GUI_ACTIVE"] / 8.0                 # summed over the 8 XCDs
+    clock = cycles / (dur_us * 1e3)                     # GHz
+    busy = m["SQ_ACTIVE_INST_VALU"] * 4.0 / 1024.0 / cycles
+    rate = m["SQ_INSTS_VALU"] / (dur_us * 1e3)          # wave-instructions per ns
+    spl = 2 if "k_step2" in kname else 1
+    prof = {"kernel": kname, "workload": "cavity %dx%d Ra=1e6 Pr=0.71 Q=5e-6, %s" % (n, n, precision),
+            "steps_per_launch": spl, "source_digest": source_digest(), "launches": len(per[(kname, "SQ_INSTS_VALU")]),
+            "counters_per_launch": m, "trace_avg_us": dur_us, "clock_GHz": round(clock, 3),
+            "valu_busy": round(busy, 4), "valu_instructions_per_node_launch": round(m["SQ_INSTS_VALU"] * 64.0 / (n * n), 1),
+            "valu_rate_G_per_s": round(rate, 1), "valu_peak_G_per_s": VALU_PEAK_G_PER_S,
+            "valu_frac_of_peak": round(rate / VALU_PEAK_G_PER_S, 4), "command": command}
+    tag = "step_cavity%d_%s" % (n, precision)
+    with open(os.path.join(ROOT, "profiles", tag + "_valu.json"), "w") as fh:
+        json.dump(prof, fh, indent=1)
+    lines = ["# VALU issue and shader clock of the step kernel: cavity %dx%d Ra=1e6 Pr=0.71 Q=5e-6, %s"
+             % (n, n, precision), "", "Command (run from the repository root on the GPU box):", "",
+             "    " + command, "",
+             "| quantity | value |", "|---|---|",
+             "| kernel | %s (%d launches) |" % (kname, prof["launches"]),
+             "| traced duration per launch | %.1f us |" % dur_us]
+    lines += ["| %s per launch | %.4g |" % (c, m[c]) for c in sorted(m)]
+    lines += ["| shader clock: GRBM_GUI_ACTIVE / 8 XCDs / duration | %.2f GHz |" % clock,
+              "| VALU busy: SQ_ACTIVE_INST_VALU x 4 / 1024 SIMDs / cycles | %.2f |" % busy,
+              "| VALU instructions per node per launch: SQ_INSTS_VALU x 64 / nodes | %.0f |" % prof["valu_instructions_per_node_launch"],
+              "| VALU issue rate / peak (one wave-instruction per clock per CU, 256 CUs, 2.4 GHz) | %.0f / %.0f G/s = %.2f |"
+              % (rate, VALU_PEAK_G_PER_S, rate / VALU_PEAK_G_PER_S),
+              "", "Step-kernel source digest: %s" % prof["source_digest"]]
+    with open(os.path.join(ROOT, "profiles", tag + "_valu.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps({"written": tag + "_valu", "valu_busy": prof["valu_busy"], "clock_GHz": prof["clock_GHz"]}))
+
+
+def measured_valu(precision, n, steps_per_launch):
+    """VALU issue of the step kernel from the committed counter profile, or None when there
+    is no profile for this kernel source, workload and launch mode."""
+    path = os.path.join(ROOT, "profiles", "step_cavity%d_%s_valu.json" % (n, precision))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        prof = json.load(fh)
+    if prof.get("source_digest") != source_digest() or prof.get("steps_per_launch", 1) != steps_per_launch:
+        return None
+    return {k: prof[k] for k in ("valu_busy", "clock_GHz", "valu_instructions_per_node_launch",
+                                 "valu_rate_G_per_s", "valu_peak_G_per_s", "valu_frac_of_peak")}
+
+
 def cpu_baseline(prob, target_s=15.0):
     """The FP64 oracle on a 256-row strip of the same lattice and parameters, all host
     threads, steps chosen so the sample takes about target_s seconds."""
@@ -583,6 +649,11 @@ def warmstart_experiment(args):
 
 
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-valu":
+        # --summarize-valu DB PRECISION N "command"
+        a = sys.argv[2:]
+        summarize_valu(a[0], a[1], int(a[2]), a[3])
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-profiles":
         # --summarize-profiles TRACE_DB FETCH_DB WRITE_DB PRECISION N "cmd1" "cmd2" "cmd3"
         a = sys.argv[2:]
@@ -679,6 +750,7 @@ def main():
     log("bench: reference copy %.0f GB/s" % copy_gbs)
 
     traffic = measured_traffic(args.precision, args.n, spl)
+    valu = measured_valu(args.precision, args.n, spl)
     out = {
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 5),
@@ -704,7 +776,10 @@ def main():
                      "note": ("achieved = algorithmic bytes of the launch's %d step(s) (%d B per node update) / "
                               "launch time; with two steps per launch the intermediate state stays in LDS, so the "
                               "launch moves about half of them: traffic (measured) / launch time = traffic_rate_GBs"
-                              % (spl, bpl))},
+                              % (spl, bpl)),
+                     # the kernel's VALU issue from the committed counter profile: what bounds it
+                     # once two steps share one HBM pass
+                     "valu": valu},
     }
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on the host")
