@@ -116,7 +116,7 @@ def measured_traffic(precision, n, steps_per_launch):
 VALU_PEAK_G_PER_S = 256 * 2.4  # wave-instructions per ns: one per clock per CU, 256 CUs at 2.4 GHz
 
 
-def summarize_valu(db, precision, n, command):
+def summarize_valu(db, precision, n, command, out_dir=None):
     """Write the VALU issue and shader-clock summary of the step kernel under profiles/ from
     one rocprofv3 run with --kernel-trace and the counters GRBM_GUI_ACTIVE,
     SQ_ACTIVE_INST_VALU, SQ_BUSY_CU_CYCLES and SQ_INSTS_VALU."""
@@ -145,7 +145,8 @@ def summarize_valu(db, precision, n, command):
             "valu_rate_G_per_s": round(rate, 1), "valu_peak_G_per_s": VALU_PEAK_G_PER_S,
             "valu_frac_of_peak": round(rate / VALU_PEAK_G_PER_S, 4), "command": command}
     tag = "step_cavity%d_%s" % (n, precision)
-    with open(os.path.join(ROOT, "profiles", tag + "_valu.json"), "w") as fh:
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    with open(os.path.join(out_dir, tag + "_valu.json"), "w") as fh:
         json.dump(prof, fh, indent=1)
     lines = ["# VALU issue and shader clock of the step kernel: cavity %dx%d Ra=1e6 Pr=0.71 Q=5e-6, %s"
              % (n, n, precision), "", "Command (run from the repository root on the GPU box):", "",
@@ -160,7 +161,7 @@ def summarize_valu(db, precision, n, command):
               "| VALU issue rate / peak (one wave-instruction per clock per CU, 256 CUs, 2.4 GHz) | %.0f / %.0f G/s = %.2f |"
               % (rate, VALU_PEAK_G_PER_S, rate / VALU_PEAK_G_PER_S),
               "", "Step-kernel source digest: %s" % prof["source_digest"]]
-    with open(os.path.join(ROOT, "profiles", tag + "_valu.md"), "w") as fh:
+    with open(os.path.join(out_dir, tag + "_valu.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print(json.dumps({"written": tag + "_valu", "valu_busy": prof["valu_busy"], "clock_GHz": prof["clock_GHz"]}))
 
@@ -201,7 +202,7 @@ def cpu_baseline(prob, target_s=15.0):
                       % (strip["nx"], strip["ny"], prob["nx"], prob["ny"], nsteps, dt)}
 
 
-def summarize_profiles(trace_db, fetch_db, write_db, precision, n, command):
+def summarize_profiles(trace_db, fetch_db, write_db, precision, n, command, out_dir=None):
     """Write the kernel-time and HBM-traffic summaries under profiles/ from rocprofv3
     databases: one kernel-trace run and two counter runs (FETCH_SIZE, WRITE_SIZE). The
     counters are scaled by what they read for the reference copy (known bytes)."""
@@ -254,8 +255,9 @@ def summarize_profiles(trace_db, fetch_db, write_db, precision, n, command):
         "trace_avg_us": step_row[3], "trace_calls": step_row[1],
         "commands": command,
     }
-    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    with open(os.path.join(ROOT, "profiles", tag + "_hbm_traffic.json"), "w") as fh:
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, tag + "_hbm_traffic.json"), "w") as fh:
         json.dump(prof, fh, indent=1)
     lines = ["# Kernel time and HBM traffic: %s" % prof["workload"], "",
              "Commands (run from the repository root on the GPU box):", ""]
@@ -276,7 +278,7 @@ def summarize_profiles(trace_db, fetch_db, write_db, precision, n, command):
               % (BYTES_PER_LUP[precision], n * n, spl, alg),
               "| traffic / algorithmic | %.4f |" % (traffic / alg),
               "", "Step-kernel source digest: %s" % prof["source_digest"]]
-    with open(os.path.join(ROOT, "profiles", tag + "_rocprof.md"), "w") as fh:
+    with open(os.path.join(out_dir, tag + "_rocprof.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print(json.dumps({"written": tag, "traffic_over_algorithmic": traffic / alg}))
 
