@@ -149,7 +149,7 @@ def summarize_valu(db, precision, n, command, out_dir=None):
     with open(os.path.join(out_dir, tag + "_valu.json"), "w") as fh:
         json.dump(prof, fh, indent=1)
     lines = ["# VALU issue and shader clock of the step kernel: cavity %dx%d Ra=1e6 Pr=0.71 Q=5e-6, %s"
-             % (n, n, precision), "", "Command (run from the repository root on the GPU box):", "",
+             % (n, n, precision), "", "Command (run from the repository root on the MI355X):", "",
              "    " + command, "",
              "| quantity | value |", "|---|---|",
              "| kernel | %s (%d launches) |" % (kname, prof["launches"]),
@@ -260,7 +260,7 @@ def summarize_profiles(trace_db, fetch_db, write_db, precision, n, command, out_
     with open(os.path.join(out_dir, tag + "_hbm_traffic.json"), "w") as fh:
         json.dump(prof, fh, indent=1)
     lines = ["# Kernel time and HBM traffic: %s" % prof["workload"], "",
-             "Commands (run from the repository root on the GPU box):", ""]
+             "Commands (run from the repository root on the MI355X):", ""]
     lines += ["    " + c for c in command]
     lines += ["", "## rocprofv3 --kernel-trace --stats (top kernels)", "",
               "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
