@@ -443,11 +443,20 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
 #pragma unroll
         for (int j = 0; j < R; ++j)
             finish(a[j], b[j], X0 + lane, Y0 - 1 + wave + j * nwaves, lane + 1, wave + j * nwaves);
+        // the two ring columns: interior nodes too, each lane with its own row
+        for (int q = tid; q < 2 * T::YE; q += NT) {
+            const int lx = q < T::YE ? 0 : T::XE - 1, ly = q % T::YE;
+            const int gx = X0 - 1 + lx, gy = Y0 - 1 + ly;
+            const char* rc = stored_row(src, c.rowlen, gy);
+            float ra[9], rb9[5];
+            gather_interior<S, kBlock>(rc - rb, rc, rc + rb, stored_cols<S>(gx), ra, rb9);
+            finish(ra, rb9, gx, gy, lx, ly);
+        }
     } else {
 #pragma unroll
         for (int j = 0; j < T::YE / nwaves; ++j) advance(lane + 1, wave + j * nwaves);
+        for (int q = tid; q < 2 * T::YE; q += NT) advance(q < T::YE ? 0 : T::XE - 1, q % T::YE);
     }
-    for (int k = tid; k < 2 * T::YE; k += NT) advance(k < T::YE ? 0 : T::XE - 1, k % T::YE);
 }
 
 // Phase 2 for thread tid: the tile's own nodes advanced from LDS and stored.
