@@ -19,7 +19,8 @@ import tempfile
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE = os.path.join(ROOT, "oracle")
 PINS = ["tests/test_oracle_matrices.py", "tests/test_oracle_collision.py",
-        "tests/test_oracle_analytic.py", "tests/test_oracle_viscous.py"]
+        "tests/test_oracle_relaxation.py", "tests/test_oracle_analytic.py",
+        "tests/test_oracle_viscous.py"]
 
 # (what the mistake is, original snippet, mutated snippet)
 MUTANTS = [
@@ -45,6 +46,26 @@ MUTANTS = [
      "1.0 / (p->alpha / CT2 + 0.5)", "1.0 / (p->alpha / CS2 + 0.5)"),
     ("Eq. (8): bulk and shear parts of the 2nd-order block swapped",
      "c->S[3 * Q9 + 3] = sp; c->S[3 * Q9 + 4] = sm;", "c->S[3 * Q9 + 3] = sm; c->S[3 * Q9 + 4] = sp;"),
+    ("Eq. (8): s_3 in place of s_4 on k22",
+     "c->S[8 * Q9 + 8] = c->s_4;", "c->S[8 * Q9 + 8] = c->s_3;"),
+    ("Eq. (8): a caller's s_4 ignored (always 1)",
+     "double s_4 = isnan(p->s_4) ? 1.0 : p->s_4;", "double s_4 = 1.0;"),
+    ("Eq. (8): a caller's s_b ignored (always 1)",
+     "double s_b = isnan(p->s_b) ? 1.0 : p->s_b;", "double s_b = 1.0;"),
+    ("Eq. (8): bulk rate ignored, the trace relaxed at s_nu",
+     "double sp = 0.5 * (c->s_b + c->s_nu), sm = 0.5 * (c->s_b - c->s_nu);",
+     "double sp = c->s_nu, sm = 0.0;"),
+    ("Eq. (8): s- with the wrong sign",
+     "double sp = 0.5 * (c->s_b + c->s_nu), sm = 0.5 * (c->s_b - c->s_nu);",
+     "double sp = 0.5 * (c->s_b + c->s_nu), sm = 0.5 * (c->s_nu - c->s_b);"),
+    ("Eq. (8): the collision uses s_4 = 1 whatever the rates say",
+     "c->s_3 = r[2]; c->s_4 = r[3];", "c->s_3 = r[2]; c->s_4 = 1.0;"),
+    ("S_T: lambda_2 on the first thermal moments",
+     "c->ST[1 * Q5 + 1] = c->l1; c->ST[2 * Q5 + 2] = c->l1;",
+     "c->ST[1 * Q5 + 1] = c->l2; c->ST[2 * Q5 + 2] = c->l2;"),
+    ("S_T: lambda_1 on the second thermal moments",
+     "c->ST[3 * Q5 + 3] = c->l2; c->ST[4 * Q5 + 4] = c->l2;",
+     "c->ST[3 * Q5 + 3] = c->l1; c->ST[4 * Q5 + 4] = c->l1;"),
     ("Eq. (25): source correction of T with a wrong sign",
      "    T += 0.5 * Qn;", "    T -= 0.5 * Qn;"),
     ("Eq. (2): buoyancy with a wrong sign",
