@@ -2,19 +2,23 @@
 
 Workload: the 4096 x 4096 differentially heated cavity (Ra = 1e6, Pr = 0.71,
 uniform heat source Q = 5e-6, Dirichlet side walls, adiabatic top and bottom,
-U = 0.1), FP32 populations. This is the configuration whose working set
-(1.88 GB of populations) exceeds the 256 MB Infinity Cache, so its HBM
-roofline fraction is meaningful. One step = one collide-and-stream update of
-every node; the FP32 default launch advances two steps per kernel launch
-(k_step2, the first step's tile and halo kept in LDS), so the roofline's
-algorithmic bytes per launch are 112 B x nodes x 2. The diagnostics reduction
-(residual, wall heat flux, mass, NaN check) runs every --diag-every steps inside
-the timed region.
+U = 0.1), FP32 populations (or FP16 weight-shifted storage with --precision
+fp16s). This is the configuration whose working set (1.88 GB of populations)
+exceeds the 256 MB Infinity Cache, so its HBM roofline fraction is meaningful.
+One step = one collide-and-stream update of every node; the default launch
+advances two steps per kernel launch (k_step2, the first step's tile and halo
+kept in LDS). The timed steps are replayed from HIP graphs; the diagnostics
+reduction (residual, wall heat flux, mass, NaN check) runs every --diag-every
+steps when the timed region is that long.
 
 Prints one JSON line: MLUPS (million lattice-node updates per second, both
-distributions), the roofline of the step kernel (algorithmic 112 B per node
-update in FP32, 56 B in FP16 storage, over the kernel's average duration from
-HIP events on the solver's stream) and the FP64 oracle's rate on the host cores.
+distributions) and the roofline of the step kernel. Its `achieved` is the bytes one
+launch must move (every stored population read once and written once: 112 B per
+node in FP32, 56 B in FP16 storage, whatever the steps per launch) over the
+launch's average duration from HIP events on the solver's stream around the timed
+region. The per-step algorithmic rate (bytes of one-step updates times the steps a
+launch advances) is reported beside it as `effective_GBs`. `cpu_baseline` times
+the FP64 oracle on the host cores.
 """
 import argparse
 import json
@@ -35,18 +39,60 @@ def log(*a):
 
 
 def time_steps(torch, s, steps, diag_every):
-    """Wall-clock time of `steps` steps (diagnostics every diag_every steps)."""
+    """Runs `steps` steps (diagnostics after every diag_every steps) and returns the
+    wall-clock seconds, the milliseconds between HIP events recorded on the solver's
+    stream at the start and the end, and the number of diagnostics calls made."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    done = 0
+    e0.record(s.stream)
+    done = diags = 0
     while done < steps:
         n = min(diag_every, steps - done) if diag_every > 0 else steps - done
         s.step(n)
         done += n
         if diag_every > 0 and done % diag_every == 0:
             s.diagnostics()
+            diags += 1
+    e1.record(s.stream)
     torch.cuda.synchronize()
-    return time.perf_counter() - t0
+    return time.perf_counter() - t0, e0.elapsed_time(e1), diags
+
+
+def launches_of(steps, spl):
+    """Step-kernel launches of `steps` steps at spl steps per launch."""
+    return steps // 2 + steps % 2 if spl == 2 else steps
+
+
+def graph_steps(steps, diag_every):
+    """Steps per replayed graph: the stretch between diagnostics (or the whole run), even."""
+    g = min(steps, diag_every) if diag_every > 0 else steps
+    return g - g % 2
+
+
+def arithmetic_dtype(precision):
+    """The arithmetic type of the collision for a storage precision: FP64 registers for
+    FP32 storage, FP32 for FP16 weight-shifted storage."""
+    return {"fp32": "f64", "fp16s": "f32"}[precision]
+
+
+def host_cpu():
+    """Host CPU model and the logical CPUs this process may run on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
 
 
 def kernel_avg_ms(torch, s, launches):
@@ -181,12 +227,14 @@ def measured_valu(precision, n, steps_per_launch):
 
 
 def cpu_baseline(prob, target_s=15.0):
-    """The FP64 oracle on a 256-row strip of the same lattice and parameters, all host
-    threads, steps chosen so the sample takes about target_s seconds."""
-    import numpy as np
+    """The FP64 oracle on a 256-row strip of the same lattice and parameters, steps chosen
+    so the sample takes about target_s seconds. Threads: OMP_NUM_THREADS when set (the GPU
+    machine sets 16, its share of the host), else every CPU this process may use."""
     import oracle
     strip = dict(prob, ny=256)
-    nth = oracle.default_threads()
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    model, ncpu, usable = host_cpu()
+    nth = int(env) if env.isdigit() and int(env) > 0 else usable
     o = oracle.Sim(strip, nthreads=nth)
     o.step(1)                      # first step: thread start-up
     t0 = time.perf_counter()
@@ -199,7 +247,9 @@ def cpu_baseline(prob, target_s=15.0):
     lups = strip["nx"] * strip["ny"] * nsteps
     return {"value": round(lups / dt / 1e6, 3), "unit": "MLUPS", "cores": nth, "kind": "oracle",
             "sample": "FP64 oracle, %dx%d strip of the %dx%d cavity (same parameters), %d steps, %.1f s"
-                      % (strip["nx"], strip["ny"], prob["nx"], prob["ny"], nsteps, dt)}
+                      % (strip["nx"], strip["ny"], prob["nx"], prob["ny"], nsteps, dt),
+            "threads_from": "OMP_NUM_THREADS" if env.isdigit() and int(env) > 0 else "affinity",
+            "host_cpu_model": model, "host_logical_cpus": ncpu, "host_cpus_usable": usable}
 
 
 def summarize_profiles(trace_db, fetch_db, write_db, precision, n, command, out_dir=None):
@@ -733,54 +783,73 @@ def main():
     if args.launch:
         v = [int(x) for x in args.launch.split(",")]
         s.set_launch(*v)
+    gsteps = graph_steps(args.steps, args.diag_every)
+    if gsteps > 0:
+        s.set_graph(gsteps)          # instantiates both graphs before anything is timed
     T0 = torch.from_numpy(W.cavity_initial_T(prob, seed=12345).astype(np.float32))
     s.init(T=T0)
-    log("bench: %dx%d %s, warmup %d" % (args.n, args.n, args.precision, args.warmup))
+    log("bench: %dx%d %s, warmup %d, graphs of %d steps" % (args.n, args.n, args.precision, args.warmup, gsteps))
     time_steps(torch, s, args.warmup, args.diag_every)
     log("bench: timing %d steps" % args.steps)
-    wall = time_steps(torch, s, args.steps, args.diag_every)
+    wall, ev_ms, diags = time_steps(torch, s, args.steps, args.diag_every)
     nodes = args.n * args.n
     mlups = nodes * args.steps / wall / 1e6
-    log("bench: %.3f ms/step, %.1f MLUPS" % (wall / args.steps * 1e3, mlups))
-    kms, spl = kernel_avg_ms(torch, s, args.kernel_launches)
+    spl = s.get_launch()["steps_per_launch"]
+    launches = launches_of(args.steps, spl)
+    kms = ev_ms / launches           # the timed region's launches, HIP events on the solver's stream
+    log("bench: %.4f ms/step, %.1f MLUPS; %d launches, %.4f ms per launch (events), %d diagnostics"
+        % (wall / args.steps * 1e3, mlups, launches, kms, diags))
+    kms_iso, _ = kernel_avg_ms(torch, s, args.kernel_launches)
     d = s.diagnostics()
     bpl = BYTES_PER_LUP[args.precision]
-    achieved = bpl * nodes * spl / (kms * 1e-3) / 1e9
-    log("bench: step kernel %.4f ms avg per launch of %d step(s), %.0f GB/s algorithmic, nan %d"
-        % (kms, spl, achieved, d.nan_count))
+    must_move = bpl * nodes                       # every population read once, written once
+    achieved = must_move / (kms * 1e-3) / 1e9
+    effective = bpl * nodes * spl / (kms * 1e-3) / 1e9
+    log("bench: step kernel %.4f ms per launch of %d step(s) (%.4f ms over %d back-to-back launches), "
+        "%.0f GB/s moved, %.0f GB/s per-step algorithmic, nan %d"
+        % (kms, spl, kms_iso, args.kernel_launches, achieved, effective, d.nan_count))
     copy_gbs, copy_ms = copy_ceiling(torch, clbm)
     log("bench: reference copy %.0f GB/s" % copy_gbs)
 
     traffic = measured_traffic(args.precision, args.n, spl)
     valu = measured_valu(args.precision, args.n, spl)
+    if diags:
+        diag_text = "the diagnostics reduction after every %d steps (%d calls in the timed region)" % (
+            args.diag_every, diags)
+    else:
+        diag_text = "no diagnostics in the timed region"
     out = {
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": arithmetic_dtype(args.precision),
         "data": "synthetic",
         "config": {"workload": "cavity %dx%d Ra=1e6 Pr=0.71 Q=5e-6 U=0.1, %s populations, "
-                               "fused collide-and-stream, diagnostics every %d steps"
-                               % (args.n, args.n, args.precision, args.diag_every),
-                   "nx": args.n, "ny": args.n, "precision": args.precision,
-                   "launch": s.get_launch()},
+                               "fused collide-and-stream, %d step(s) per launch, %s replayed from graphs "
+                               "of %d steps, %s"
+                               % (args.n, args.n, args.precision, spl, "steps" if gsteps else "no steps",
+                                  gsteps, diag_text),
+                   "nx": args.n, "ny": args.n, "storage": args.precision,
+                   "collision_arithmetic": arithmetic_dtype(args.precision),
+                   "launch": s.get_launch(), "graph_steps": gsteps, "diagnostics_calls": diags},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     # measured HBM bytes over the same launch time: how busy HBM really is
-                     # (below `achieved` when a launch advances two steps on one read)
-                     "traffic_rate_GBs": None if traffic is None else round(traffic / (kms * 1e-3) / 1e9, 1),
-                     "algorithmic_bytes_per_launch": bpl * nodes * spl,
+                     "bytes_per_launch": must_move,
                      "kernel": "k_step2" if spl == 2 else "k_step", "steps_per_launch": spl,
-                     "kernel_avg_ms": round(kms, 5), "bytes_per_lup": bpl,
+                     "kernel_avg_ms": round(kms, 5), "launches_timed": launches,
+                     "kernel_avg_ms_back_to_back": round(kms_iso, 5),
+                     # measured HBM bytes over the same launch time
+                     "traffic_rate_GBs": None if traffic is None else round(traffic / (kms * 1e-3) / 1e9, 1),
+                     # one-step updates the launch performs, at the one-step kernel's bytes each
+                     "effective_GBs": round(effective, 1), "bytes_per_lup": bpl,
                      "copy_ceiling_GBs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4),
-                     "note": ("achieved = algorithmic bytes of the launch's %d step(s) (%d B per node update) / "
-                              "launch time; with two steps per launch the intermediate state stays in LDS, so the "
-                              "launch moves about half of them: traffic (measured) / launch time = traffic_rate_GBs"
-                              % (spl, bpl)),
-                     # the kernel's VALU issue from the committed counter profile: what bounds it
-                     # once two steps share one HBM pass
+                     "note": ("achieved = bytes one launch must move (each of the %d B per node read once and "
+                              "written once) / launch time from HIP events around the timed region; a launch "
+                              "advances %d step(s), so the per-step algorithmic rate is effective_GBs"
+                              % (bpl, spl)),
+                     # the kernel's VALU issue from the committed counter profile
                      "valu": valu},
     }
     if not args.no_cpu_baseline:

@@ -194,7 +194,9 @@ clbm_status clbm_get_step(const clbm_handle* h, long* step);
 clbm_status clbm_set_launch(clbm_handle* h, const clbm_launch* launch);
 clbm_status clbm_get_launch(const clbm_handle* h, clbm_launch* launch);
 /* steps_per_graph = 0 launches every step on the stream; an even value > 0 replays
- * graphs of that many steps (the default is 0). */
+ * graphs of that many steps (the default is 0). Both graphs (one per starting buffer)
+ * are instantiated by this call; clbm_set_launch drops them and the next clbm_step
+ * rebuilds the one it needs. */
 clbm_status clbm_set_graph(clbm_handle* h, int steps_per_graph);
 
 /* Plain device-to-device copy of `bytes` bytes (one 16-byte load and store per thread;

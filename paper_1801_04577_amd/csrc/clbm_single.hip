@@ -731,6 +731,16 @@ clbm_status clbm_set_graph(clbm_handle* h, int steps_per_graph)
     if (!h || steps_per_graph < 0 || (steps_per_graph % 2) != 0) return CLBM_ERR_INVALID_ARG;
     drop_graphs(h);
     h->graph_steps = steps_per_graph;
+    // both graphs (starting from either buffer) are instantiated here, so that a later
+    // clbm_step replays them without building anything
+    for (int start = 0; start < 2 && steps_per_graph > 0; ++start) {
+        const clbm_status st = build_graph(h, start);
+        if (st != CLBM_OK) {
+            drop_graphs(h);
+            h->graph_steps = 0;
+            return st;
+        }
+    }
     return CLBM_OK;
 }
 
