@@ -72,9 +72,10 @@ def graph_steps(steps, diag_every):
 
 
 def arithmetic_dtype(precision):
-    """The arithmetic type of the collision for a storage precision: FP64 registers for
-    FP32 storage, FP32 for FP16 weight-shifted storage."""
-    return {"fp32": "f64", "fp16s": "f32"}[precision]
+    """The arithmetic type of the collision: FP32 for both storage precisions (with FP32
+    storage, the incoming population plus its change is formed exactly in FP64 before the
+    unbiased rounding into FP32)."""
+    return {"fp32": "f32", "fp16s": "f32"}[precision]
 
 
 def host_cpu():
@@ -195,7 +196,7 @@ def summarize_valu(db, precision, n, command, out_dir=None):
     with open(os.path.join(out_dir, tag + "_valu.json"), "w") as fh:
         json.dump(prof, fh, indent=1)
     lines = ["# VALU issue and shader clock of the step kernel: cavity %dx%d Ra=1e6 Pr=0.71 Q=5e-6, %s"
-             % (n, n, precision), "", "Command (run from the repository root on the MI355X):", "",
+             % (n, n, precision), "", "Command (on the MI355X, where /root/repo is the repository):", "",
              "    " + command, "",
              "| quantity | value |", "|---|---|",
              "| kernel | %s (%d launches) |" % (kname, prof["launches"]),
@@ -310,7 +311,7 @@ def summarize_profiles(trace_db, fetch_db, write_db, precision, n, command, out_
     with open(os.path.join(out_dir, tag + "_hbm_traffic.json"), "w") as fh:
         json.dump(prof, fh, indent=1)
     lines = ["# Kernel time and HBM traffic: %s" % prof["workload"], "",
-             "Commands (run from the repository root on the MI355X):", ""]
+             "Commands (on the MI355X, where /root/repo is the repository):", ""]
     lines += ["    " + c for c in command]
     lines += ["", "## rocprofv3 --kernel-trace --stats (top kernels)", "",
               "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
@@ -324,9 +325,15 @@ def summarize_profiles(trace_db, fetch_db, write_db, precision, n, command, out_
               "| WRITE_SIZE, reference copy of 2 GiB (KiB/dispatch) | %.1f |" % w_copy,
               "| scale factors (known bytes / counter) | fetch %.4f, write %.4f |" % (sf, sw),
               "| traffic per launch (bytes) | %.4e |" % traffic,
-              "| algorithmic bytes per launch (%d B x %d nodes x %d step(s)) | %.4e |"
+              "| bytes a launch must move (%d B x %d nodes: each population read once, written once) | %.4e |"
+              % (BYTES_PER_LUP[precision], n * n, BYTES_PER_LUP[precision] * n * n),
+              "| traffic / bytes a launch must move | %.4f |" % (traffic / (BYTES_PER_LUP[precision] * n * n)),
+              "| rate: bytes a launch must move / traced average duration | %.1f GB/s (%.3f of 8 TB/s) |"
+              % (BYTES_PER_LUP[precision] * n * n / (step_row[3] * 1e-6) / 1e9,
+                 BYTES_PER_LUP[precision] * n * n / (step_row[3] * 1e-6) / 1e9 / HBM_PEAK_GBS),
+              "| per-step algorithmic bytes of the launch (%d B x %d nodes x %d step(s)) | %.4e |"
               % (BYTES_PER_LUP[precision], n * n, spl, alg),
-              "| traffic / algorithmic | %.4f |" % (traffic / alg),
+              "| traffic / per-step algorithmic | %.4f |" % (traffic / alg),
               "", "Step-kernel source digest: %s" % prof["source_digest"]]
     with open(os.path.join(out_dir, tag + "_rocprof.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")

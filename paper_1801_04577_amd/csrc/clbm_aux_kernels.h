@@ -38,8 +38,8 @@ __global__ void __launch_bounds__(256) k_init(S* __restrict__ dst, const Lattice
     typename Wide<S>::type fa[9], tb[5];
     equilibrium(drho, vx, vy, th, c.T0, a, b);
     NodeMacro m;
-    if (c.viscous) collide<typename Wide<S>::type, true>(c, a, b, fa, tb, m);
-    else collide(c, a, b, fa, tb, m);
+    if (c.viscous) collide<float, true, typename Wide<S>::type>(c, a, b, fa, tb, m);
+    else collide<float, false, typename Wide<S>::type>(c, a, b, fa, tb, m);
     store_node(dst, c, x, y, fa, tb);
 }
 

@@ -51,10 +51,10 @@ __global__ void __launch_bounds__(1024) k_batch_step(const BatchInst* __restrict
             NodeMacro m;
             if (c.viscous) {
                 gather_node<float, true, unsigned>(src, c, x, y, a, b);
-                collide<double, true>(c, a, b, fa, tb, m);
+                collide<float, true, double>(c, a, b, fa, tb, m);
             } else {
                 gather_node<float, false, unsigned>(src, c, x, y, a, b);
-                collide(c, a, b, fa, tb, m);
+                collide<float, false, double>(c, a, b, fa, tb, m);
             }
             store_node<float, unsigned>(dst, c, x, y, fa, tb);
         }

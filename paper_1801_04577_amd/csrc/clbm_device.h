@@ -103,8 +103,12 @@ __device__ __forceinline__ unsigned mix32(unsigned h)
     return h;
 }
 
-// Arithmetic type of the collision for a storage type: FP64 for FP32 storage and FP32
-// for binary16 storage (whose rounding, 2^-11, dominates FP32's).
+// Type of a post-collision value before it is rounded into the storage type S: FP64 for
+// FP32 storage, FP32 for binary16 storage. The collision itself is FP32 arithmetic for
+// both; it yields the change of every population, and the stored value is the incoming
+// population plus its change, formed exactly in this wider type (two FP32 numbers sum
+// exactly in FP64, up to exponent gaps beyond 29 bits) and then rounded once, without
+// bias, into storage.
 template <typename S> struct Wide;
 template <> struct Wide<float> { typedef double type; };
 template <> struct Wide<__half> { typedef float type; };
@@ -114,15 +118,28 @@ template <> struct Wide<__half> { typedef float type; };
 __device__ __forceinline__ unsigned hash_bits(double x) { return (unsigned)__double_as_longlong(x); }
 __device__ __forceinline__ unsigned hash_bits(float x) { return __float_as_uint(x); }
 
-// x rounded into the storage type S with the unbiased rounding; r is a uniform 32-bit
-// variate.
-// FP64 -> FP32: add the top 29 bits of r to the 52-bit mantissa and truncate the 29 bits
-// FP32 does not keep; the conversion of the truncated value is then exact. The magnitude
-// rounds up with probability (discarded bits)/2^29.
+// Uniform variates of the unbiased rounding into S, from one 32-bit node hash h: value k
+// takes base(h) ^ key(k), with distinct constant keys (each variate is uniform when h is).
+// FP32 storage needs 29 random bits (the bits FP64 has and FP32 drops), taken from the
+// top of h; binary16 storage takes all 32 bits (the conversion reads the top ones).
+template <typename S> struct RandBits;
+template <> struct RandBits<float> {
+    static __device__ __forceinline__ unsigned base(unsigned h) { return h >> 3; }
+    static constexpr unsigned key(int k) { return ((unsigned)k * 0x9E3779B9u) >> 3; }
+};
+template <> struct RandBits<__half> {
+    static __device__ __forceinline__ unsigned base(unsigned h) { return h; }
+    static constexpr unsigned key(int k) { return (unsigned)k * 0x9E3779B9u; }
+};
+
+// x rounded into the storage type S with the unbiased rounding; r is the value's variate.
+// FP64 -> FP32: add the 29-bit r below the FP32 part of the 52-bit mantissa and truncate
+// the 29 bits FP32 does not keep; the conversion of the truncated value is then exact.
+// The magnitude rounds up with probability (discarded bits)/2^29.
 __device__ __forceinline__ float sr_round(double x, unsigned r)
 {
     unsigned long long bits = (unsigned long long)__double_as_longlong(x);
-    bits += (unsigned long long)(r >> 3);
+    bits += (unsigned long long)r;
     bits &= ~0x1FFFFFFFull;
     return (float)__longlong_as_double((long long)bits);
 }
@@ -161,9 +178,9 @@ struct NodeMacro {
 // Delta k20 = -lambda_2 (k20 - c_T^2 T) + (1 - lambda_2/2) c_T^2 Q (k02 alike); the
 // change is shifted back to raw moments (inverse of Eq. 17) and to populations
 // (inverse of Eq. 16) and added to the incoming populations, tb = b + Delta g.
-template <typename R>
+template <typename R, typename P>
 __device__ __forceinline__ void collide_thermal(const LatticeConst& c, const float b[5], R ux,
-                                                R uy, R Q, R src2, R tb[5])
+                                                R uy, R Q, R src2, P tb[5])
 {
     const R T0 = kv<R>(c.T0, c.d_T0);
     const R b0 = b[0], b1 = b[1], b2 = b[2], b3 = b[3], b4 = b[4];
@@ -188,12 +205,13 @@ __device__ __forceinline__ void collide_thermal(const LatticeConst& c, const flo
     const R r01 = d01 + uy * Q;
     const R r20 = d20 + ux * (R(2.0) * d10 + ux * Q);
     const R r02 = d02 + uy * (R(2.0) * d01 + uy * Q);
-    // Inverse of Eq. (16), added to the incoming populations.
-    tb[0] = b0 + (Q - r20 - r02);
-    tb[1] = b1 + R(0.5) * (r20 + r10);
-    tb[3] = b3 + R(0.5) * (r20 - r10);
-    tb[2] = b2 + R(0.5) * (r02 + r01);
-    tb[4] = b4 + R(0.5) * (r02 - r01);
+    // Inverse of Eq. (16): the change of each population, added to the incoming one in P
+    // (the factor 1/2 is exact and applied in P with the sum).
+    tb[0] = P(b[0]) + P(Q - r20 - r02);
+    tb[1] = P(b[1]) + P(0.5) * P(r20 + r10);
+    tb[3] = P(b[3]) + P(0.5) * P(r20 - r10);
+    tb[2] = P(b[2]) + P(0.5) * P(r02 + r01);
+    tb[4] = P(b[4]) + P(0.5) * P(r02 - r01);
 }
 
 // Viscous dissipation nu [(d_x u_y + d_y u_x)^2 + (d_x u_x - d_y u_y)^2] (Sec. 3.2 uses
@@ -213,13 +231,17 @@ __device__ __forceinline__ R dissipation(R coef, R c11, R c2d, R rho)
 
 // Cascaded collision of one node. On entry a[9], b[5] hold the pre-collision
 // deviations at time t; on exit fa[9] and tb[5] hold the post-collision flow and
-// temperature deviations in the wide type R, to be rounded into storage by store_node.
+// temperature deviations in the type P, to be rounded into storage by store_node.
 // m receives rho - 1, u and T - T0 at time t.
-// R is wider than the storage (FP64 for FP32 storage, FP32 for FP16 storage) so that the
-// only rounding left in a time step is the unbiased one into storage: a body force or a
-// heat source adds the same non-representable amount every step, and round-to-nearest of
-// those increments in storage-precision arithmetic would otherwise bias the velocity and
-// the temperature by a fixed fraction of an ulp per step.
+// The arithmetic type R gives the change of each population; the change is added to the
+// incoming population in P (FP64 for FP32 storage, exact), so that the only rounding of
+// a stored value is the unbiased one into storage: a body force or a heat source adds
+// the same non-representable amount every step, and round-to-nearest of the sum in
+// storage precision would bias the velocity and the temperature by a fixed fraction of
+// an ulp per step. The change itself may carry R's rounding: it is the sum of small
+// terms (the moments are taken on deviations and the first central moments are fixed by
+// the force), so its error is relative to the change, far below an ulp of the stored
+// population, and on the conserved moments it does not accumulate beyond that.
 // The collision is evaluated as a change: Eq. (7) changes the central moments by
 // Delta = -S (k - k_eq) + (I - S/2) C, which vanishes on the conserved k00 and is the
 // force on k10, k01; the change is shifted back to raw moments with N(-u) (the inverse
@@ -227,9 +249,9 @@ __device__ __forceinline__ R dissipation(R coef, R c11, R c2d, R rho)
 // populations: f* = f + M^-1 N(-u) Delta.
 // VH: the heat source is Q plus the local viscous dissipation (needs g_beta = 0, so
 // that the force does not depend on the temperature the source produces).
-template <typename R, bool VH = false>
+template <typename R, bool VH = false, typename P = R>
 __device__ __forceinline__ void collide(const LatticeConst& c, const float a_in[9], const float b[5],
-                                        R fa[9], R tb[5], NodeMacro& m)
+                                        P fa[9], P tb[5], NodeMacro& m)
 {
     const R third = R(1) / R(3), ninth = R(1) / R(9);
     // Eq. (25): T = sum g + Q/2; sum g = T0 + sum b.
@@ -308,20 +330,21 @@ __device__ __forceinline__ void collide(const LatticeConst& c, const float a_in[
     const R R12 = g12 + ux * g02;
     const R R22 = (g22 + tx * g12) + ux2 * g02;
 
-    // Inverse of Eq. (6a), added to the incoming populations.
+    // Inverse of Eq. (6a): the change of each population, added to the incoming one in P.
     const R v1 = R20 - R22, u1 = Fx - R12;
     const R v2 = R02 - R22, u2 = Fy - R21;
     const R s1 = R11 + R22, s2 = R21 + R12;
     const R t1 = R22 - R11, t2 = R21 - R12;
-    fa[0] = a[0] - (v1 + R02);
-    fa[1] = a[1] + R(0.5) * (v1 + u1);
-    fa[3] = a[3] + R(0.5) * (v1 - u1);
-    fa[2] = a[2] + R(0.5) * (v2 + u2);
-    fa[4] = a[4] + R(0.5) * (v2 - u2);
-    fa[5] = a[5] + R(0.25) * (s1 + s2);
-    fa[7] = a[7] + R(0.25) * (s1 - s2);
-    fa[6] = a[6] + R(0.25) * (t1 + t2);
-    fa[8] = a[8] + R(0.25) * (t1 - t2);
+    // (the factors 1/2 and 1/4 are exact, so they are applied in P together with the sum)
+    fa[0] = P(a_in[0]) - P(v1 + R02);
+    fa[1] = P(a_in[1]) + P(0.5) * P(v1 + u1);
+    fa[3] = P(a_in[3]) + P(0.5) * P(v1 - u1);
+    fa[2] = P(a_in[2]) + P(0.5) * P(v2 + u2);
+    fa[4] = P(a_in[4]) + P(0.5) * P(v2 - u2);
+    fa[5] = P(a_in[5]) + P(0.25) * P(s1 + s2);
+    fa[7] = P(a_in[7]) + P(0.25) * P(s1 - s2);
+    fa[6] = P(a_in[6]) + P(0.25) * P(t1 + t2);
+    fa[8] = P(a_in[8]) + P(0.25) * P(t1 - t2);
 
     if constexpr (VH) {
         const R Qn = kv<R>(c.Q, c.d_Q) + dissipation<R>(kv<R>(c.vh_pre, c.d_vh_pre), c11, n20 - n02, rho);

@@ -181,10 +181,10 @@ __device__ __forceinline__ void gather_node(const S* __restrict__ src, const Lat
 }
 
 // Round the post-collision state of one node (x, y) into the storage type: the
-// deviations, computed wider than the storage, go through the unbiased rounding of
+// deviations, formed wider than the storage, go through the unbiased rounding of
 // sr_round. One hash per node mixes the node's coordinates with the sum of the bits of
-// all 14 results (equal results do not cancel in a sum); the k-th value takes
-// h + k * 0x9E3779B9 (a Weyl sequence), each uniform on its own. The coordinates give
+// all 14 results (equal results do not cancel in a sum); the k-th value takes the hash
+// xor a constant key of its own (RandBits), each uniform on its own. The coordinates give
 // nodes in equal states independent variates: a uniform lattice whose increments are far
 // below a unit in the last place would otherwise round every node alike and could keep
 // rounding to the same state. A state that no longer changes is still stored identically.
@@ -197,11 +197,11 @@ __device__ __forceinline__ void round_node(const typename Wide<S>::type fa[9],
     for (int i = 0; i < 9; ++i) acc += hash_bits(fa[i]);
 #pragma unroll
     for (int i = 0; i < 5; ++i) acc += hash_bits(tb[i]);
-    const unsigned h = mix32(acc);
+    const unsigned r = RandBits<S>::base(mix32(acc));
 #pragma unroll
-    for (int i = 0; i < 9; ++i) out[i] = sr_round(fa[i], h + (unsigned)i * 0x9E3779B9u);
+    for (int i = 0; i < 9; ++i) out[i] = sr_round(fa[i], r ^ RandBits<S>::key(i));
 #pragma unroll
-    for (int i = 0; i < 5; ++i) out[9 + i] = sr_round(tb[i], h + (unsigned)(9 + i) * 0x9E3779B9u);
+    for (int i = 0; i < 5; ++i) out[9 + i] = sr_round(tb[i], r ^ RandBits<S>::key(9 + i));
 }
 
 // Store the post-collision state of node (x, y), nontemporal; O as in GlobalMem.
@@ -327,7 +327,7 @@ __global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __r
             W fa[9], tb[5];
             NodeMacro m;
             gather_interior<S, kBlock>(rc - rb, rc, rc + rb, k, a, b);
-            collide<W, VH>(c, a, b, fa, tb, m);
+            collide<float, VH, W>(c, a, b, fa, tb, m);
             store_node_at(reinterpret_cast<S*>(stored_row(dst, c.rowlen, yw + r) + k.c), fa, tb, x, yw + r);
         }
         return;
@@ -341,7 +341,7 @@ __global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __r
             W fa[9], tb[5];
             gather_node<S, VH, O>(src, c, x, y, a, b);
             NodeMacro m;
-            collide<W, VH>(c, a, b, fa, tb, m);
+            collide<float, VH, W>(c, a, b, fa, tb, m);
             store_node<S, O>(dst, c, x, y, fa, tb);
         }
     }
@@ -405,7 +405,7 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
     auto finish = [&](const float a[9], const float b[5], int gx, int gy, int lx, int ly) {
         W fa[9], tb[5];
         NodeMacro m;
-        collide<W, VH>(c, a, b, fa, tb, m);
+        collide<float, VH, W>(c, a, b, fa, tb, m);
         S v[14];
         round_node<S>(fa, tb, v, gx, gy);
         const unsigned o = (unsigned)ly * T::XE + lx;
@@ -485,7 +485,7 @@ __device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeC
             W fa[9], tb[5];
             NodeMacro m;
             gather_interior<S, T::P>(rc - rb, rc, rc + rb, k, a, b);
-            collide<W, VH>(c, a, b, fa, tb, m);
+            collide<float, VH, W>(c, a, b, fa, tb, m);
             store_node_at(reinterpret_cast<S*>(stored_row(dst, c.rowlen, Y0 + ly) + own), fa, tb, gx, Y0 + ly);
         }
     } else if (gx < c.nx) {
@@ -498,7 +498,7 @@ __device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeC
             W fa[9], tb[5];
             NodeMacro m;
             gather_mem<VH>(mem, c, gx, gy, a, b);
-            collide<W, VH>(c, a, b, fa, tb, m);
+            collide<float, VH, W>(c, a, b, fa, tb, m);
             store_node<S, O>(dst, c, gx, gy, fa, tb);
         }
     }
