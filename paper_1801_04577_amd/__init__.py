@@ -107,6 +107,7 @@ def _declare(L):
         "clbm_macros": (st, [_VP, _FP, _FP, _FP, _FP]),
         "clbm_populations": (st, [_VP, _FP, _FP]),
         "clbm_diagnostics": (st, [_VP, ctypes.POINTER(clbm_diag)]),
+        "clbm_diagnostics_noalloc": (st, [_VP, ctypes.POINTER(clbm_diag)]),
         "clbm_state_bytes": (st, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
         "clbm_save": (st, [_VP, _VP]),
         "clbm_load": (st, [_VP, _VP, ctypes.c_long]),
@@ -321,12 +322,15 @@ class Solver:
         _check(lib().clbm_populations(self._h, _addr(f), _addr(g)), "clbm_populations")
         return f, g
 
-    def diagnostics(self, raise_on_nan=False):
+    def diagnostics(self, raise_on_nan=False, noalloc=False):
+        """clbm_diagnostics, or with noalloc clbm_diagnostics_noalloc (partial sums in the
+        library's own device array instead of the workspace)."""
         d = clbm_diag()
-        st = lib().clbm_diagnostics(self._h, ctypes.byref(d))
+        name = "clbm_diagnostics_noalloc" if noalloc else "clbm_diagnostics"
+        st = getattr(lib(), name)(self._h, ctypes.byref(d))
         if st == CLBM_ERR_NAN and not raise_on_nan:
             return d
-        _check(st, "clbm_diagnostics")
+        _check(st, name)
         return d
 
     def state_bytes(self):

@@ -317,7 +317,44 @@ struct clbm_handle {
     int graph_steps;
     hipGraphExec_t gexec[2];  // graph_steps steps starting from buffer 0 / 1
     hipGraph_t graph[2];
+    double* scratch;     // this GPU's copy of the library's diagnostics scratch
 };
+
+// ---------------------------------------------------------------------------
+// Library-owned scratch of clbm_diagnostics_noalloc
+// ---------------------------------------------------------------------------
+
+// The diagnostics reduction's per-workgroup partial sums (kDiagMaxBlocks x kDiagSums) and
+// its final sums (kDiagSums), in a fixed device array instead of the caller's workspace:
+// 155 KB. Each GPU the library runs on holds its own copy until the process ends. Every
+// call on one GPU shares that copy, so calls that overlap on one GPU race (order them on
+// one stream). Nothing in it has to start at zero: a call writes every partial it reads.
+constexpr size_t kScratchDoubles = (size_t)kDiagMaxBlocks * kDiagSums + kDiagSums;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices];
+
+// Device address of the scratch on `device`, which must be the current device: resolved
+// once per device, then reused. In host code the array's own name is not a device
+// address; only this pointer may be handed to kernels.
+static clbm_status scratch_address(int device, double** out)
+{
+    if (device < 0 || device >= kMaxDevices) return CLBM_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_last_hip_error(e, "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+            return CLBM_ERR_HIP;
+        }
+        g_scratch_ptr[device] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return CLBM_OK;
+}
 
 namespace {
 
@@ -523,6 +560,18 @@ clbm_status clbm_create(const clbm_params* p, void* d_workspace, size_t bytes, v
     h->launch = default_launch(p->precision);
     h->graph_steps = 0;
     h->snap_step = -1;
+    int device = -1;
+    const hipError_t de = hipGetDevice(&device);
+    if (de != hipSuccess) {
+        set_last_hip_error(de, "hipGetDevice", __FILE__, __LINE__);
+        delete h;
+        return CLBM_ERR_HIP;
+    }
+    st = scratch_address(device, &h->scratch);
+    if (st != CLBM_OK) {
+        delete h;
+        return st;
+    }
     st = clbm_init_from_fields(h, nullptr, nullptr, nullptr, nullptr);
     if (st != CLBM_OK) {
         delete h;
@@ -607,23 +656,28 @@ clbm_status clbm_populations(clbm_handle* h, float* d_f, float* d_g)
     return CLBM_OK;
 }
 
-clbm_status clbm_diagnostics(clbm_handle* h, clbm_diag* out)
+}  // extern "C"
+
+namespace {
+
+// The diagnostics reduction with its partial sums in `partial` (kDiagMaxBlocks x
+// kDiagSums doubles) and its final sums in `result` (kDiagSums doubles).
+clbm_status diagnostics_into(clbm_handle* h, double* partial, double* result, clbm_diag* out)
 {
-    if (!h || !out) return CLBM_ERR_INVALID_ARG;
     const size_t n = (size_t)h->p.nx * h->p.ny;
     const int blocks = (int)std::min<size_t>((n + kDiagBlock - 1) / kDiagBlock, kDiagMaxBlocks);
     const int have = h->snap_step >= 0 ? 1 : 0;
     if (h->p.precision == CLBM_FP16_SHIFTED)
         hipLaunchKernelGGL(k_diag<__half>, dim3(blocks), dim3(kDiagBlock), 0, h->stream,
-                           (const __half*)h->buf[h->cur], h->c, h->snap, have, h->partial);
+                           (const __half*)h->buf[h->cur], h->c, h->snap, have, partial);
     else
         hipLaunchKernelGGL(k_diag<float>, dim3(blocks), dim3(kDiagBlock), 0, h->stream,
-                           (const float*)h->buf[h->cur], h->c, h->snap, have, h->partial);
+                           (const float*)h->buf[h->cur], h->c, h->snap, have, partial);
     CLBM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, h->stream, h->partial, blocks, h->result);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, h->stream, partial, blocks, result);
     CLBM_HIP(hipGetLastError());
     double r[kDiagSums];
-    CLBM_HIP(hipMemcpyAsync(r, h->result, sizeof r, hipMemcpyDeviceToHost, h->stream));
+    CLBM_HIP(hipMemcpyAsync(r, result, sizeof r, hipMemcpyDeviceToHost, h->stream));
     CLBM_HIP(hipStreamSynchronize(h->stream));
     std::memset(out, 0, sizeof *out);
     out->step = h->step;
@@ -647,6 +701,27 @@ clbm_status clbm_diagnostics(clbm_handle* h, clbm_diag* out)
     out->nan_count = (long)r[13];
     h->snap_step = h->step;
     return out->nan_count > 0 ? CLBM_ERR_NAN : CLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+clbm_status clbm_diagnostics(clbm_handle* h, clbm_diag* out)
+{
+    if (!h || !out) return CLBM_ERR_INVALID_ARG;
+    return diagnostics_into(h, h->partial, h->result, out);
+}
+
+clbm_status clbm_diagnostics_noalloc(clbm_handle* h, clbm_diag* out)
+{
+    if (!h || !out) return CLBM_ERR_INVALID_ARG;
+    if (!h->scratch) return CLBM_ERR_HIP;
+    const size_t n = (size_t)h->p.nx * h->p.ny;
+    const size_t parts = std::min<size_t>((n + kDiagBlock - 1) / kDiagBlock, kDiagMaxBlocks);
+    // the reduction grid is capped at kDiagMaxBlocks workgroups, so every lattice fits
+    if ((parts + 1) * kDiagSums > kScratchDoubles) return CLBM_ERR_BUFFER_TOO_SMALL;
+    return diagnostics_into(h, h->scratch, h->scratch + (size_t)kDiagMaxBlocks * kDiagSums, out);
 }
 
 clbm_status clbm_stream_copy(void* d_dst, const void* d_src, size_t bytes, void* hip_stream)
