@@ -340,6 +340,68 @@ def summarize_profiles(trace_db, fetch_db, write_db, precision, n, command, out_
     print(json.dumps({"written": tag, "traffic_over_algorithmic": traffic / alg}))
 
 
+def standin_errors(args):
+    """The 512 x 512 stand-in of the 4096^2 workload (same Ra, Pr, Q and walls, U = 0.1 rule,
+    seeded noise): FP32 and FP16-shifted storage on the GPU and the FP64 oracle on the host,
+    advanced together over the configuration's 20 000 steps. At each checkpoint, per field,
+    max |gpu - oracle| / max |oracle| (u as the vector (u_x, u_y)) and max |rho - rho_oracle|."""
+    import numpy as np
+    import torch
+    import paper_1801_04577_amd as clbm
+    import workloads as W
+    import oracle
+
+    prob = W.cavity(512, Ra=1e6, Pr=0.71, Q=5e-6)
+    T = W.cavity_initial_T(prob, seed=12345).astype(np.float32)
+    o = oracle.Sim(prob, T=T.astype(np.float64))
+    gpu = {}
+    for name, prec in (("fp32", clbm.CLBM_FP32), ("fp16s", clbm.CLBM_FP16_SHIFTED)):
+        g = clbm.Solver(prob, prec)
+        g.init(T=torch.from_numpy(T))
+        gpu[name] = g
+    checkpoints = [int(c) for c in args.standin_checkpoints.split(",")]
+    rows = []
+    t0 = time.perf_counter()
+    for c in checkpoints:
+        while o.t < c:
+            n = min(1000, c - o.t)
+            o.step(n)
+            for g in gpu.values():
+                g.step(n)
+            log("standin: %d steps, %.0f s" % (o.t, time.perf_counter() - t0))
+        ro, uxo, uyo, To = o.macros()
+        umax = float(np.sqrt(uxo ** 2 + uyo ** 2).max())
+        Tmax = float(np.abs(To).max())
+        row = {"steps": c, "umax": umax, "Tmax": Tmax}
+        for name, g in gpu.items():
+            rg, uxg, uyg, Tg = [t.cpu().numpy().astype(np.float64) for t in g.macros()]
+            row[name] = {"u": float(np.sqrt((uxg - uxo) ** 2 + (uyg - uyo) ** 2).max() / umax),
+                         "T": float(np.abs(Tg - To).max() / Tmax),
+                         "rho_abs": float(np.abs(rg - ro).max())}
+        rows.append(row)
+        log("standin: %d steps: fp32 u %.2e T %.2e, fp16s u %.2e T %.2e"
+            % (c, row["fp32"]["u"], row["fp32"]["T"], row["fp16s"]["u"], row["fp16s"]["T"]))
+    out = {"workload": "cavity 512x512 Ra=1e6 Pr=0.71 Q=5e-6 U=0.1, seeded noise 1e-4 (seed 12345), "
+                       "stand-in of the 4096x4096 workload",
+           "oracle_threads": o.nthreads, "seconds": round(time.perf_counter() - t0, 1), "checkpoints": rows}
+    if args.standin_out:
+        lines = ["# Error of the GPU storage types against the FP64 oracle: 512^2 stand-in, 20 000 steps", "",
+                 "Command (on the MI355X, where /root/repo is the repository):", "",
+                 "    cd /root/repo && python bench.py --standin --standin-out %s" % args.standin_out, "",
+                 "Workload: %s. Error per field: max over nodes of |gpu - oracle| / max over nodes of "
+                 "|oracle| (u as the vector (u_x, u_y)); rho absolute." % out["workload"], "",
+                 "| steps | max u | FP32 u | FP32 T | FP32 rho | FP16s u | FP16s T | FP16s rho |",
+                 "|---|---|---|---|---|---|---|---|"]
+        for r in rows:
+            lines.append("| %d | %.3e | %.2e | %.2e | %.1e | %.2e | %.2e | %.1e |"
+                         % (r["steps"], r["umax"], r["fp32"]["u"], r["fp32"]["T"], r["fp32"]["rho_abs"],
+                            r["fp16s"]["u"], r["fp16s"]["T"], r["fp16s"]["rho_abs"]))
+        lines += ["", "Oracle threads: %d; wall time %.0f s." % (o.nthreads, out["seconds"])]
+        with open(args.standin_out, "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+    return out
+
+
 def small_configs(args):
     """The cache-resident configurations on the GPU (their working sets fit the 256 MB
     Infinity Cache, so they are launch-bound and get no HBM fraction; steps are replayed
@@ -735,6 +797,10 @@ def main():
     ap.add_argument("--sweep-steps", type=int, default=200)
     ap.add_argument("--sweep-max-steps", type=int, default=200000)
     ap.add_argument("--write-cache", default="", help="path of the autotuner cache (JSON lines)")
+    ap.add_argument("--standin", action="store_true",
+                    help="512^2 stand-in: FP32 and FP16 storage against the oracle over 20 000 steps")
+    ap.add_argument("--standin-checkpoints", default="1000,5000,10000,20000")
+    ap.add_argument("--standin-out", default="", help="write the error table (markdown) here")
     ap.add_argument("--warmstart", action="store_true", help="run the learned warm-start experiment only")
     ap.add_argument("--net", action="store_true", help="time the warm-start network's kernels only")
     ap.add_argument("--net-steps", type=int, default=50)
@@ -775,6 +841,9 @@ def main():
         return
     if args.net:
         print(json.dumps({"metric": METRIC, "network": net_throughput(args)}), flush=True)
+        return
+    if args.standin:
+        print(json.dumps({"metric": METRIC, "standin": standin_errors(args)}), flush=True)
         return
     if args.warmstart:
         r = warmstart_experiment(args)

@@ -95,6 +95,57 @@ def test_gradients_match_reference():
     assert worst < 5e-2
 
 
+def _elementwise(got, want):
+    """Worst |got - want| / (2^-8 (|want| + max |want|)) over a tensor."""
+    scale = 2.0 ** -8 * (np.abs(want) + np.abs(want).max())
+    return float((np.abs(got - want) / np.maximum(scale, 1e-300)).max())
+
+
+def test_production_shape_elementwise():
+    """Batch 2 at 128 x 128, the training shape of the warm start: the first two levels
+    run the LDS-staged convolutions with 64-column pixel blocks (k_conv_lds<2, 64> and
+    <4, 64>), the deeper ones the 32- and 16-column blocks, and the weight gradients take
+    the split counts of 32 768 pixels. Reference: the network with BF16 storage of the
+    operands (oracle/net.py, quant=True), which rounds at the points where the kernels
+    store BF16. In the first layers the two differ only by FP32 versus FP64 accumulation
+    (about 1e-7 of a sum) and by the few BF16 roundings it moves across a boundary (one
+    BF16 unit, 2^-8 of the element). Each such element shifts the sums it feeds by about
+    sqrt(p) of their BF16 unit when a fraction p of the inputs moved, so the fraction of
+    diverging roundings grows like p -> sqrt(p) from layer to layer and within a few
+    layers nearly every element differs by up to half a unit: two independent BF16
+    roundings per layer. Over the 15 layers (30 with the backward pass) that gives a
+    deviation of a few 1e-3 of a tensor's rms, whose 4.5-sigma tail over the 1e5 elements
+    of a tensor is about 5 units of 2^-8 of its rms, while its largest element is about
+    3.5 rms. Every output element and every element of every weight and bias gradient must
+    therefore lie within 4 x 2^-8 (|ref| + max |ref| of its tensor); the per-layer worst
+    ratio to 2^-8 (|ref| + max |ref|) is printed with the relative L2 errors against the
+    unrounded FP64 network. A wrong tap or halo moves whole terms of a sum (a third of a
+    3x3 stencil at a block edge) and exceeds the bound many times over."""
+    import torch
+    B, H = 2, 128
+    params, xs, ts = setup(batch=B, H=H, seed=11)
+    n = gpu_net(B, H)
+    n.set_params(torch.from_numpy(flatten(params).astype(np.float32)))
+    y = n.forward(torch.from_numpy(xs.astype(np.float32))).cpu().numpy().astype(np.float64)
+    loss = n.backward(torch.from_numpy(ts.astype(np.float32)))
+    got = unflatten(n.grads().cpu().numpy().astype(np.float64), params)
+    want_y = np.stack([ref.forward(params, x, quant=True) for x in xs])
+    want_loss, want = ref.loss_and_grads(params, xs, ts, quant=True)
+    exact_y = np.stack([ref.forward(params, x) for x in xs])
+    _, exact = ref.loss_and_grads(params, xs, ts)
+    ey = _elementwise(y, want_y)
+    print("128^2 batch 2: output worst %.3f of the bound (rel L2 vs exact %.2e); loss %.6e vs %.6e"
+          % (ey, rel(y, exact_y), loss, want_loss), flush=True)
+    worst = ey
+    for k, ((gw, gb), (ww, wb), (xw, xb)) in enumerate(zip(got, want, exact)):
+        rw, rb = _elementwise(gw, ww), _elementwise(gb, wb)
+        print("layer %2d  dW worst %.3f  db worst %.3f  (rel L2 vs exact: dW %.2e db %.2e)"
+              % (k, rw, rb, rel(gw, xw), rel(gb, xb)), flush=True)
+        worst = max(worst, rw, rb)
+    assert loss == pytest.approx(want_loss, rel=1e-3)
+    assert worst <= 4.0
+
+
 def test_training_reduces_loss():
     import torch
     params, xs, ts = setup(seed=5)

@@ -7,7 +7,7 @@ averaged) by a parabola through the three nodes around the discrete maximum, pos
 divided by H with node centres at (j + 1/2); Nu is the mean heat flux into the cold wall
 in units of k dT/H, from the wall gradient of Eq. (27). Tolerances: the two other
 lattice Boltzmann solutions printed in Table 1 differ from the CLBM rows by about 1-3%,
-so Nu and u_max are held to 1%, v_max to 2% and positions to 1.5/H.
+so Nu and u_max are held to 1%, v_max to 2% and positions to one node spacing, 1/H.
 """
 import json
 import math
@@ -88,8 +88,10 @@ def test_table1(k):
     assert q["Nu_flux"] == pytest.approx(q["Nu"], rel=5e-3)
     assert q["u_max"] == pytest.approx(g["u_max"][k], rel=1e-2)
     assert q["v_max"] == pytest.approx(g["v_max"][k], rel=2e-2)
-    assert abs(q["y_max"] - g["y_max"][k]) <= 1.5 / n
-    assert abs(q["x_max"] - g["x_max"][k]) <= 1.5 / n
+    print("position offsets in nodes: y_max %.2f, x_max %.2f"
+          % ((q["y_max"] - g["y_max"][k]) * n, (q["x_max"] - g["x_max"][k]) * n), flush=True)
+    assert abs(q["y_max"] - g["y_max"][k]) <= 1.0 / n
+    assert abs(q["x_max"] - g["x_max"][k]) <= 1.0 / n
 
 
 def test_cavity_256_to_residual():
@@ -147,3 +149,31 @@ def test_wall_flux_closed_form(alpha):
     assert d.wall_flux[2] == pytest.approx(QL, rel=1e-5)
     assert -alpha * d.dTdn[2] == pytest.approx(QL, rel=1e-5)
     assert abs(d.wall_flux[3]) <= 1e-5 * QL and abs(alpha * d.dTdn[3]) <= 1e-5 * QL
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-5), (1, 1e-2)])
+def test_channel_64x32_10000_steps(precision, tol):
+    """The 64 x 32 body-force channel with a uniform heat source, started at rest, after
+    its full 10 000 steps: u and T against the continuum start-up series (Sec. 3.2 flow
+    field; the series of the oracle's own test), within 1e-3 of the field maximum (lattice
+    dispersion of the decaying modes and the half-step force and source of the initial
+    state), and against the oracle at the parity bar of the storage type."""
+    from parity import field_errors, run_gpu, run_oracle
+    from test_oracle_analytic import channel_series, y_nodes
+    prob = W.channel()
+    H, steps = prob["ny"], 10000
+    s = run_gpu(prob, steps, precision=precision)
+    o = run_oracle(prob, steps)
+    rho, ux, uy, T = [t.cpu().numpy().astype(np.float64) for t in s.macros()]
+    y = y_nodes(H)
+    u_a = channel_series(y, float(steps), H, prob["Fx"], prob["nu"])
+    T_a = channel_series(y, float(steps), H, prob["Q"], prob["alpha"])
+    eu = float(np.abs(ux - u_a[:, None]).max() / u_a.max())
+    eT = float(np.abs(T - T_a[:, None]).max() / T_a.max())
+    e = field_errors(o, s)
+    print("channel 64x32, %d steps, %s: vs series u %.2e T %.2e (1e-3); vs oracle u %.2e T %.2e"
+          % (steps, "fp32" if precision == 0 else "fp16s", eu, eT, e["u"], e["T"]), flush=True)
+    # FP16 storage carries its own error (held to 1e-2 against the oracle) on top
+    series_tol = 1e-3 if precision == 0 else 1e-2
+    assert eu < series_tol and eT < series_tol
+    assert e["u"] <= tol and e["T"] <= tol

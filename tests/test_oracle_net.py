@@ -60,3 +60,39 @@ def test_gradients_match_finite_differences():
                 assert g == pytest.approx(fd, rel=1e-6, abs=1e-9), (k, which, idx)
                 checked += 1
     assert checked >= 60
+
+
+def test_bf16_round_matches_torch():
+    """The BF16 rounding of the reference's quantized mode is round-to-nearest-even, as
+    torch's float -> bfloat16 conversion (a library routine) defines it: random values
+    over many magnitudes and both signs, and exact ties."""
+    import torch
+    rng = np.random.default_rng(7)
+    x = rng.normal(size=4000) * 10.0 ** rng.integers(-30, 30, 4000)
+    ties = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -(1 + 2.0 ** -8), 3 * 2.0 ** -9 + 2.0 ** -1,
+                     255.5, 256.5, 257.0, 2.0 ** -126 * (1 + 2.0 ** -8)])
+    for v in (x, ties):
+        want = torch.from_numpy(v.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+        np.testing.assert_array_equal(net.bf16_round(v), want)
+
+
+def test_quantized_network_stays_within_bf16_error():
+    """quant=True rounds operands to BF16 (8 significant bits, 2^-9 relative) at every
+    storage point: outputs and gradients move from the exact network's (pinned by finite
+    differences above) by more than round-off, but by a few units of 2^-8 of each tensor's
+    largest element at most (gradients up to about ten: a ReLU whose input lies within the
+    rounding of zero passes or stops a whole gradient element)."""
+    rng = np.random.default_rng(3)
+    cin, cout, widths, H = 4, 3, (8, 16, 16, 32), 32
+    params = net.init_params(cin, cout, widths, seed=4)
+    params = [(w, rng.normal(scale=0.05, size=b.shape)) for w, b in params]
+    xs = rng.normal(size=(2, cin, H, H))
+    ts = rng.normal(scale=0.5, size=(2, cout, H, H))
+    y0, yq = net.forward(params, xs[0]), net.forward(params, xs[0], quant=True)
+    assert 1e-6 * np.abs(y0).max() < np.abs(yq - y0).max() <= 8 * 2.0 ** -8 * np.abs(y0).max()
+    l0, g0 = net.loss_and_grads(params, xs, ts)
+    lq, gq = net.loss_and_grads(params, xs, ts, quant=True)
+    assert lq == pytest.approx(l0, rel=1e-2)
+    for (w0, b0), (wq, bq) in zip(g0, gq):
+        for a, b in ((wq, w0), (bq, b0)):
+            assert np.abs(a - b).max() <= 16 * 2.0 ** -8 * np.abs(b).max()
