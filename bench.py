@@ -498,7 +498,8 @@ def batched_sweep(args):
     inits = [{"T": torch.from_numpy((p["T0"] + W.noise_field(sd, p["nx"], p["ny"], 1e-4)).astype(np.float32))}
              for p, sd in sets]
     log("batched: %d cavities, %d nodes" % (len(probs), nodes))
-    b = clbm.Batch(probs)
+    prec = clbm.CLBM_FP16_SHIFTED if args.precision == "fp16s" else clbm.CLBM_FP32
+    b = clbm.Batch(probs, precision=prec)
     cache = args.write_cache or None
     if cache and os.path.exists(cache):
         os.remove(cache)
@@ -518,7 +519,7 @@ def batched_sweep(args):
     # the same cavities advanced one launch per cavity per step
     solvers = []
     for p, f in zip(probs, inits):
-        sv = clbm.Solver(p)
+        sv = clbm.Solver(p, prec)
         sv.init(**f)
         solvers.append(sv)
     for sv in solvers:
@@ -538,21 +539,68 @@ def batched_sweep(args):
     for i, f in enumerate(inits):
         b.init(i, **f)
     t0 = time.perf_counter()
-    steps, status = b.run(max_steps=args.sweep_max_steps, tol=1e-7, K=1000)
+
+    def progress(st, names):
+        log("batched: run to 1e-7: %.0f s, running %d, converged %d, diverged %d, max_steps %d, "
+            "max steps %d" % (time.perf_counter() - t0, names.count("running"), names.count("converged"),
+                              names.count("diverged"), names.count("max_steps"), max(st)))
+    steps, status = b.run(max_steps=args.sweep_max_steps, tol=1e-7, K=1000, chunk=50000, progress=progress)
     t_run = time.perf_counter() - t0
     lups = sum(st * p["nx"] * p["ny"] for st, p in zip(steps, probs))
-    counts = {k: status.count(k) for k in set(status)}
-    log("batched: run to 1e-7: %s in %.1f s, %.1f MLUPS" % (counts, t_run, lups / t_run / 1e6))
-    return {"workload": "%d cavities (sides 64-512, a<=b<=2a; Ra 1e3-1e6 log-uniform; Pr 0.7-7; "
-                        "Q 0-1e-4), FP32" % len(probs),
-            "nodes": nodes, "tile": best,
-            "mlups_batched": round(mlups_batch, 1), "mlups_loop_of_launches": round(mlups_loop, 1),
-            "speedup_vs_loop": round(mlups_batch / mlups_loop, 2),
-            "run_to_residual": {"tol": 1e-7, "K": 1000, "max_steps": args.sweep_max_steps,
-                                "status_counts": counts, "seconds": round(t_run, 2),
-                                "mlups": round(lups / t_run / 1e6, 1),
-                                "steps_min": int(min(steps)), "steps_max": int(max(steps)),
-                                "steps_median": float(np.median(steps))}}
+    counts = {k: status.count(k) for k in ("converged", "diverged", "max_steps", "running")}
+    under = [i for i, p in enumerate(probs) if p["meta"]["under_resolved"]]
+    under_counts = {k: [status[i] for i in under].count(k) for k in ("converged", "diverged", "max_steps")}
+    log("batched: run to 1e-7: %s in %.1f s, %.1f MLUPS; under-resolved (tau_nu < 0.52): %d %s"
+        % (counts, t_run, lups / t_run / 1e6, len(under), under_counts))
+    res = {"workload": "%d cavities (sides 64-512, a<=b<=2a; Ra 1e3-1e6 log-uniform; Pr 0.7-7; "
+                       "Q 0-1e-4), %s storage" % (len(probs), args.precision),
+           "nodes": nodes, "tile": best,
+           "mlups_batched": round(mlups_batch, 1), "mlups_loop_of_launches": round(mlups_loop, 1),
+           "speedup_vs_loop": round(mlups_batch / mlups_loop, 2),
+           "run_to_residual": {"tol": 1e-7, "K": 1000, "max_steps": args.sweep_max_steps,
+                               "status_counts": counts, "seconds": round(t_run, 2),
+                               "mlups": round(lups / t_run / 1e6, 1),
+                               "steps_min": int(min(steps)), "steps_max": int(max(steps)),
+                               "steps_median": float(np.median(steps)),
+                               "under_resolved": len(under), "under_resolved_status": under_counts}}
+    if args.sweep_summary:
+        write_batch_summary(cache, res, args.sweep_summary)
+    if args.sweep_out:
+        with open(args.sweep_out, "w") as fh:
+            json.dump(dict(res, per_instance=[
+                {"nx": p["nx"], "ny": p["ny"], "Ra": p["meta"]["Ra"], "Pr": p["meta"]["Pr"], "Q": p["Q"],
+                 "tau_nu": p["meta"]["tau_nu"], "steps": st, "status": sn}
+                for p, st, sn in zip(probs, steps, status)]), fh, indent=1)
+    return res
+
+
+def write_batch_summary(cache, res, out):
+    """Markdown summary of a batched-sweep run: the autotuner's candidates (from its cache
+    file, fastest first) and the run to the residual."""
+    lines = ["# Batched step: autotuner sweep and run to residual, %s" % res["workload"], "",
+             "Command (on the MI355X, where /root/repo is the repository):", "",
+             "    cd /root/repo && " + " ".join(["python", "bench.py"] + sys.argv[1:]), "",
+             "Nodes: %d. Batched %.1f MLUPS against %.1f for a loop of per-cavity launches (%.2fx)."
+             % (res["nodes"], res["mlups_batched"], res["mlups_loop_of_launches"], res["speedup_vs_loop"]), ""]
+    if cache and os.path.exists(cache):
+        rows = [json.loads(l) for l in open(cache)]
+        best = [r for r in rows if r.get("best")]
+        cand = sorted((r for r in rows if not r.get("best")), key=lambda r: r["ms_per_step"])
+        lines += ["## Autotuner candidates (signature %s), fastest first" % (best[-1]["signature"] if best else "?"),
+                  "", "| tile_x | tile_y | steps/launch | persistent_wgs (0 = one per tile) | XCD bands | ms/step | MLUPS |",
+                  "|---|---|---|---|---|---|---|"]
+        lines += ["| %d | %d | %d | %d | %d | %.4f | %.1f |" % (r["tile_x"], r["tile_y"], r["steps_per_launch"],
+                                                              r["persistent_wgs"], r["xcd_bands"],
+                                                              r["ms_per_step"], r["mlups"]) for r in cand]
+        lines.append("")
+    rr = res["run_to_residual"]
+    lines += ["## Run of every cavity to residual %.0e (graph of K = %d steps, on-device retirement, cap %d steps)"
+              % (rr["tol"], rr["K"], rr["max_steps"]), "",
+              "| quantity | value |", "|---|---|"]
+    lines += ["| %s | %s |" % (k, rr[k]) for k in ("status_counts", "seconds", "mlups", "steps_min", "steps_median",
+                                                 "steps_max", "under_resolved", "under_resolved_status")]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
 
 
 def net_flops_per_sample(H, W, cin=8, cout=3, widths=(32, 64, 128, 256)):
@@ -701,9 +749,20 @@ def warmstart_experiment(args):
         b = clbm.Batch(tprobs)
         for i, f in enumerate(inits):
             b.init(i, **f)
+        # Nu of every instance at each chunk boundary (a multiple of K, where the run's own
+        # residual snapshot equals the state, so reading the diagnostics does not disturb it)
+        history = []
+
+        def track(tag, offset):
+            cb = progress(tag)
+
+            def f(st, names):
+                cb(st, names)
+                history.append(([o + x for o, x in zip(offset, st)], ws.nusselt_numbers(b, tprobs)))
+            return f
         t0 = time.perf_counter()
-        steps, status = b.run(max_steps=args.ws_max_steps_eval, tol=1e-7, K=1000, chunk=20000,
-                              progress=progress("evaluate %s" % key))
+        steps, status = b.run(max_steps=args.ws_max_steps_eval, tol=1e-7, K=1000, chunk=args.ws_chunk,
+                              progress=track("evaluate %s" % key, [0] * len(tprobs)))
         dt = time.perf_counter() - t0
         nu = ws.nusselt_numbers(b, tprobs)
         out[key] = {"steps": steps, "status": status, "nu": nu, "seconds": round(dt, 1)}
@@ -712,10 +771,11 @@ def warmstart_experiment(args):
             # reach the same steady state
             t0 = time.perf_counter()
             steps_r, status_r = b.run(max_steps=args.ws_max_steps_eval, tol=args.ws_refine_tol, K=1000,
-                                      chunk=20000, progress=progress("refine %s" % key))
+                                      chunk=args.ws_chunk, progress=track("refine %s" % key, steps))
             out[key].update(refine_steps=steps_r, refine_status=status_r,
                             refine_nu=ws.nusselt_numbers(b, tprobs),
                             refine_seconds=round(time.perf_counter() - t0, 1))
+        out[key]["history"] = history
         del b
     both = [i for i in range(len(tprobs))
             if out["cold"]["status"][i] == "converged" and out["warm"]["status"][i] == "converged"]
@@ -766,6 +826,38 @@ def warmstart_experiment(args):
             rec.update(cold_refined_nu=out["cold"]["refine_nu"][i], warm_refined_nu=out["warm"]["refine_nu"][i],
                        cold_refine_steps=out["cold"]["refine_steps"][i],
                        warm_refine_steps=out["warm"]["refine_steps"][i])
+        # steps to the tighter residual, and steps until Nu stays within 1e-3 of the steady
+        # value (the cold start's Nu at the tighter residual), from the Nu recorded at every
+        # chunk boundary
+        c9 = np.array([out["cold"]["steps"][i] + out["cold"]["refine_steps"][i] for i in rb], dtype=float)
+        w9 = np.array([out["warm"]["steps"][i] + out["warm"]["refine_steps"][i] for i in rb], dtype=float)
+
+        def settle(key, i, ref):
+            """First recorded step from which Nu of instance i stays within 1e-3 of ref."""
+            first = None
+            for st, nus in out[key]["history"]:
+                if abs(nus[i] - ref) <= 1e-3 * abs(ref):
+                    first = st[i] if first is None else first
+                else:
+                    first = None
+            return first
+        sc_nu, sw_nu = [], []
+        for k, i in enumerate(rb):
+            sc_nu.append(settle("cold", i, rc[k]))
+            sw_nu.append(settle("warm", i, rc[k]))
+        ok = [k for k in range(len(rb)) if sc_nu[k] is not None and sw_nu[k] is not None]
+        res["eval"]["refine"].update({
+            "cold_steps_to_tol_total": int(c9.sum()), "warm_steps_to_tol_total": int(w9.sum()),
+            "steps_ratio_to_tol": round(float(w9.sum() / c9.sum()), 4) if len(rb) else None,
+            "nu_settle_chunk_steps": args.ws_chunk,
+            "nu_settled_both": len(ok),
+            "cold_steps_to_nu_1e-3_total": int(sum(sc_nu[k] for k in ok)),
+            "warm_steps_to_nu_1e-3_total": int(sum(sw_nu[k] for k in ok)),
+            "steps_ratio_to_nu_1e-3": round(sum(sw_nu[k] for k in ok) / max(sum(sc_nu[k] for k in ok), 1), 4),
+            "median_ratio_to_nu_1e-3": round(float(np.median([sw_nu[k] / sc_nu[k] for k in ok])), 4) if ok else None,
+        })
+        for k, i in enumerate(rb):
+            res["eval"]["per_instance"][i].update(cold_steps_to_nu=sc_nu[k], warm_steps_to_nu=sw_nu[k])
     return res
 
 
@@ -797,6 +889,8 @@ def main():
     ap.add_argument("--sweep-steps", type=int, default=200)
     ap.add_argument("--sweep-max-steps", type=int, default=200000)
     ap.add_argument("--write-cache", default="", help="path of the autotuner cache (JSON lines)")
+    ap.add_argument("--sweep-out", default="", help="write per-instance steps and statuses (JSON)")
+    ap.add_argument("--sweep-summary", default="", help="write the autotuner and run summary (markdown)")
     ap.add_argument("--standin", action="store_true",
                     help="512^2 stand-in: FP32 and FP16 storage against the oracle over 20 000 steps")
     ap.add_argument("--standin-checkpoints", default="1000,5000,10000,20000")
@@ -816,6 +910,8 @@ def main():
     ap.add_argument("--ws-eval-side", type=int, default=512)
     ap.add_argument("--ws-save", default="", help="write the trained parameters (.npy)")
     ap.add_argument("--ws-load", default="", help="skip data generation and training; load parameters (.npy)")
+    ap.add_argument("--ws-chunk", type=int, default=10000,
+                    help="steps per batched-run call in the evaluation (Nu is recorded after each)")
     ap.add_argument("--ws-refine-tol", type=float, default=0.0,
                     help="after the runs to 1e-7, continue both to this residual and compare Nu there")
     ap.add_argument("--ws-out", default="")

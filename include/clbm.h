@@ -58,9 +58,10 @@ typedef enum {
 } clbm_status;
 
 /* Population storage. Both store deviations from the rest state (f_i - w_i and
- * g_i - T0/5). The collision arithmetic is one step wider than the storage (FP64 for
- * CLBM_FP32, FP32 for CLBM_FP16_SHIFTED) and every stored value is rounded without bias
- * (stochastic rounding, its variates a hash of the node's coordinates and results). */
+ * g_i - T0/5). The collision is FP32 arithmetic for both; the incoming population plus
+ * its change is formed exactly one step wider than the storage (FP64 for CLBM_FP32, FP32
+ * for CLBM_FP16_SHIFTED) and rounded once without bias (stochastic rounding, its variates
+ * a hash of the node's coordinates and results). */
 typedef enum { CLBM_FP32 = 0, CLBM_FP16_SHIFTED = 1 } clbm_precision;
 
 typedef enum { CLBM_PERIODIC = 0, CLBM_WALL = 1 } clbm_side_kind;
@@ -106,8 +107,9 @@ typedef struct {
  * workgroup (multiple of 64, at most 1024), rows_per_thread in {1, 2, 4}, xcd_remap != 0
  * maps consecutive tiles to the same XCD.
  * steps_per_launch = 2: two time steps per launch, the intermediate state kept in LDS
- * (rounded into the storage type exactly as a stored state) by workgroups of 512 threads
- * that own tiles of 64 x 14 nodes;
+ * (rounded into the storage type exactly as a stored state) by workgroups that own tiles
+ * of 64 x two_step_rows nodes: two_step_rows 6, 14 or 30 (256, 512 or 1024 threads; 0
+ * selects 14);
  * xcd_remap applies to these tiles too, the other fields shape only the single step that
  * ends an odd step count (256 x 1 threads, one row each, if they do not form a valid
  * shape). Both modes give bitwise identical states.
@@ -115,6 +117,7 @@ typedef struct {
 typedef struct {
     int block_x, block_y, rows_per_thread, xcd_remap;
     int steps_per_launch;
+    int two_step_rows;
 } clbm_launch;
 
 /* Diagnostics at the current time (Sec. 3.3 Nusselt number and a residual). */
@@ -232,16 +235,22 @@ enum { CLBM_INST_RUNNING = 0, CLBM_INST_CONVERGED = 1, CLBM_INST_DIVERGED = 2,
 /* Tile shape of the batched kernel. steps_per_launch = 1: tile_x * tile_y nodes per
  * workgroup, one node per thread (tile_x a multiple of 64, tile_x * tile_y <= 1024).
  * steps_per_launch = 2: two time steps per launch with the intermediate state in LDS,
- * tiles of exactly 64 x 14 nodes (tile_x = 64, tile_y = 14), 512 threads; bitwise equal
- * to one-step launches. persistent_wgs > 0 launches that many workgroups, each looping
- * over tiles; 0 launches one workgroup per tile. The default (launch NULL at create)
- * is the two-step shape with one workgroup per tile. */
+ * tiles of 64 x tile_y nodes with tile_y 6, 14 or 30 (256, 512 or 1024 threads; the LDS
+ * tile of 66 x (tile_y + 2) nodes sets how many workgroups share a CU); bitwise equal to
+ * one-step launches. persistent_wgs > 0 launches that many workgroups, each looping over
+ * tiles; 0 launches one workgroup per tile. xcd_bands = 1 deals the tile list of a
+ * two-step launch to the eight XCDs in contiguous bands (neighbouring tiles of an
+ * instance share an L2), 0 strides every workgroup over the whole list. The default
+ * (launch NULL at create) is the two-step 64 x 14 shape, one workgroup per tile, in XCD
+ * bands. */
 typedef struct {
     int tile_x, tile_y, persistent_wgs;
     int steps_per_launch;
+    int xcd_bands;
 } clbm_batch_launch;
 
-/* Host only. Workspace for n instances (all precision fields must be CLBM_FP32; each
+/* Host only. Workspace for n instances (every precision field CLBM_FP32, or every one
+ * CLBM_FP16_SHIFTED: one storage type per batch, else CLBM_ERR_UNSUPPORTED; each
  * instance's population buffer, 14 x 64 ceil(nx/64) x ny values, must hold fewer than
  * 2^32 of them, else CLBM_ERR_UNSUPPORTED). */
 clbm_status clbm_batch_workspace_bytes(int n, const clbm_params* p, size_t* bytes);
@@ -253,7 +262,9 @@ void clbm_batch_destroy(clbm_batch* b);
 /* Initial state of instance i from its fields (NULL: rest state), as clbm_init_from_fields. */
 clbm_status clbm_batch_init(clbm_batch* b, int i, const float* d_rho, const float* d_ux,
                             const float* d_uy, const float* d_T);
-/* Advances every active instance by nsteps (asynchronous). */
+/* Advances every instance by nsteps, those a clbm_batch_run has retired included (all
+ * instances share the buffer parity); the run's retirements stand for a later
+ * clbm_batch_run (asynchronous). */
 clbm_status clbm_batch_step(clbm_batch* b, int nsteps);
 /* Marks every instance running with zero steps, restores the full tile list and takes
  * the residual snapshot of the current state (asynchronous). */
@@ -276,12 +287,21 @@ clbm_status clbm_batch_macros(clbm_batch* b, int i, float* d_rho, float* d_ux, f
 clbm_status clbm_batch_diagnostics(clbm_batch* b, int i, clbm_diag* out);
 /* Host copy of instance i's last residuals {res_u, res_T}; synchronises. */
 clbm_status clbm_batch_residual(clbm_batch* b, int i, double out[2]);
-/* Times candidate tile shapes on the batch's own instances (each for `steps` steps
- * after a 2-step warm-up), keeps the fastest, and appends one JSON line per candidate
- * to cache_path when it is not NULL. Every timed step advances the instances, so call
- * it before clbm_batch_init (or re-initialise afterwards). Synchronises. */
+/* Times candidate launches on the batch's own instances (each for `steps` steps after a
+ * 2-step warm-up): one-step tiles, the three two-step tile heights with and without XCD
+ * bands, each with one workgroup per tile and with 2048 and 8192 persistent workgroups.
+ * Keeps the fastest. With cache_path (not NULL) it appends one JSON line per candidate
+ * and a last line {"signature": ..., "best": 1, ...} naming the winner; the signature is
+ * a 64-bit hash of the instance count, the storage type and every instance's (nx, ny,
+ * viscous heating). Every timed step advances the instances, so call it before
+ * clbm_batch_init (or re-initialise afterwards). Synchronises. */
 clbm_status clbm_batch_autotune(clbm_batch* b, int steps, const char* cache_path,
                                 clbm_batch_launch* best);
+/* Host only. Reads the launch that clbm_batch_autotune chose for a batch with this
+ * batch's signature from the cache file (the last "best" line that matches). *found = 1
+ * and *out filled when there is one; *found = 0 when the file or the entry is missing. */
+clbm_status clbm_batch_tune_lookup(const clbm_batch* b, const char* cache_path, clbm_batch_launch* out,
+                                   int* found);
 clbm_status clbm_batch_set_launch(clbm_batch* b, const clbm_batch_launch* launch);
 
 /* ------------------------------------------------------------------------ */

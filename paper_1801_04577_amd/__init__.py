@@ -51,7 +51,7 @@ class clbm_params(ctypes.Structure):
 class clbm_launch(ctypes.Structure):
     _fields_ = [("block_x", ctypes.c_int), ("block_y", ctypes.c_int),
                 ("rows_per_thread", ctypes.c_int), ("xcd_remap", ctypes.c_int),
-                ("steps_per_launch", ctypes.c_int)]
+                ("steps_per_launch", ctypes.c_int), ("two_step_rows", ctypes.c_int)]
 
 
 class clbm_diag(ctypes.Structure):
@@ -84,7 +84,7 @@ class clbm_problem_code(ctypes.Structure):
 
 class clbm_batch_launch(ctypes.Structure):
     _fields_ = [("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int), ("persistent_wgs", ctypes.c_int),
-                ("steps_per_launch", ctypes.c_int)]
+                ("steps_per_launch", ctypes.c_int), ("xcd_bands", ctypes.c_int)]
 
 
 _lib = None
@@ -147,6 +147,8 @@ def _declare(L):
         "clbm_batch_diagnostics": (st, [_VP, ctypes.c_int, ctypes.POINTER(clbm_diag)]),
         "clbm_batch_autotune": (st, [_VP, ctypes.c_int, ctypes.c_char_p,
                                      ctypes.POINTER(clbm_batch_launch)]),
+        "clbm_batch_tune_lookup": (st, [_VP, ctypes.c_char_p, ctypes.POINTER(clbm_batch_launch),
+                                        ctypes.POINTER(ctypes.c_int)]),
         "clbm_batch_set_launch": (st, [_VP, ctypes.POINTER(clbm_batch_launch)]),
     }
     for name, (res, args) in sig.items():
@@ -347,16 +349,18 @@ class Solver:
     def load(self, buf, step):
         _check(lib().clbm_load(self._h, _addr(buf), int(step)), "clbm_load")
 
-    def set_launch(self, block_x=256, block_y=1, rows_per_thread=1, xcd_remap=0, steps_per_launch=1):
+    def set_launch(self, block_x=256, block_y=1, rows_per_thread=1, xcd_remap=0, steps_per_launch=1,
+                   two_step_rows=0):
         L = clbm_launch(int(block_x), int(block_y), int(rows_per_thread), int(xcd_remap),
-                        int(steps_per_launch))
+                        int(steps_per_launch), int(two_step_rows))
         _check(lib().clbm_set_launch(self._h, ctypes.byref(L)), "clbm_set_launch")
 
     def get_launch(self):
         L = clbm_launch()
         _check(lib().clbm_get_launch(self._h, ctypes.byref(L)), "clbm_get_launch")
         return {"block_x": L.block_x, "block_y": L.block_y, "rows_per_thread": L.rows_per_thread,
-                "xcd_remap": L.xcd_remap, "steps_per_launch": L.steps_per_launch}
+                "xcd_remap": L.xcd_remap, "steps_per_launch": L.steps_per_launch,
+                "two_step_rows": L.two_step_rows}
 
     def set_graph(self, steps_per_graph):
         _check(lib().clbm_set_graph(self._h, int(steps_per_graph)), "clbm_set_graph")
@@ -373,15 +377,25 @@ class Solver:
             pass
 
 
+def _launch_dict(L):
+    return {"tile_x": L.tile_x, "tile_y": L.tile_y, "persistent_wgs": L.persistent_wgs,
+            "steps_per_launch": L.steps_per_launch, "xcd_bands": L.xcd_bands}
+
+
 class Batch:
     """Many lattices (own sizes and parameters) advanced together on the GPU."""
 
-    def __init__(self, probs, device="cuda", stream=None, launch=None):
+    def __init__(self, probs, device="cuda", stream=None, launch=None, precision=CLBM_FP32,
+                 tune_cache=None):
+        """precision: the storage type of every instance. launch: a dict of
+        clbm_batch_launch fields; tune_cache: a cache file written by autotune, whose
+        entry for this workload (if any) replaces the default launch."""
         import torch
         self.probs = list(probs)
         self.n = len(self.probs)
         self.device = torch.device(device)
-        self.params = (clbm_params * self.n)(*[make_params(p) for p in self.probs])
+        self.precision = precision
+        self.params = (clbm_params * self.n)(*[make_params(p, precision) for p in self.probs])
         nbytes = ctypes.c_size_t()
         _check(lib().clbm_batch_workspace_bytes(self.n, self.params, ctypes.byref(nbytes)),
                "clbm_batch_workspace_bytes")
@@ -391,7 +405,8 @@ class Batch:
         if launch:
             L = clbm_batch_launch(int(launch["tile_x"]), int(launch["tile_y"]),
                                   int(launch.get("persistent_wgs", 0)),
-                                  int(launch.get("steps_per_launch", 1)))
+                                  int(launch.get("steps_per_launch", 1)),
+                                  int(launch.get("xcd_bands", 1)))
         h = ctypes.c_void_p()
         _check(lib().clbm_batch_create(self.n, self.params, _addr(self.workspace),
                                        self.workspace.numel(), _stream_ptr(self.stream),
@@ -399,6 +414,20 @@ class Batch:
                "clbm_batch_create")
         self._h = h
         self._keep = {}
+        self.tuned_from_cache = False
+        if tune_cache and launch is None:
+            cached = self.cached_launch(tune_cache)
+            if cached is not None:
+                self.set_launch(**cached)
+                self.tuned_from_cache = True
+
+    def cached_launch(self, cache_path):
+        """The launch autotune stored for this workload in cache_path, or None."""
+        L = clbm_batch_launch()
+        found = ctypes.c_int()
+        _check(lib().clbm_batch_tune_lookup(self._h, cache_path.encode(), ctypes.byref(L),
+                                            ctypes.byref(found)), "clbm_batch_tune_lookup")
+        return _launch_dict(L) if found.value else None
 
     def init(self, i, rho=None, ux=None, uy=None, T=None):
         import torch
@@ -418,20 +447,25 @@ class Batch:
     def step(self, n=1):
         _check(lib().clbm_batch_step(self._h, int(n)), "clbm_batch_step")
 
-    def run(self, max_steps, tol, K=1000, chunk=0, progress=None):
-        """Resets and runs every instance to tol (see clbm_batch_run). With chunk > 0 the
-        run proceeds in calls of at most chunk steps and progress(steps, status) is called
-        after each. Returns (steps, status) per instance; status names from INST_STATUS."""
-        _check(lib().clbm_batch_reset(self._h), "clbm_batch_reset")
+    def run(self, max_steps, tol, K=1000, chunk=0, progress=None, reset=True, max_calls=0):
+        """Runs every instance to tol (see clbm_batch_run), after clbm_batch_reset unless
+        reset is False (then the previous run resumes). With chunk > 0 the run proceeds
+        in calls of at most chunk steps and progress(steps, status) is called after each;
+        max_calls > 0 stops after that many calls. Returns (steps, status) per instance;
+        status names from INST_STATUS."""
+        if reset:
+            _check(lib().clbm_batch_reset(self._h), "clbm_batch_reset")
         steps = (ctypes.c_long * self.n)()
         status = (ctypes.c_int * self.n)()
+        calls = 0
         while True:
             _check(lib().clbm_batch_run(self._h, int(max_steps), float(tol), int(K), int(chunk), steps,
                                         status), "clbm_batch_run")
+            calls += 1
             names = [INST_STATUS[s] for s in status]
             if progress is not None:
                 progress(list(steps), names)
-            if chunk <= 0 or "running" not in names:
+            if chunk <= 0 or "running" not in names or (max_calls and calls >= max_calls):
                 return list(steps), names
 
     def macros(self, i):
@@ -453,8 +487,9 @@ class Batch:
         _check(lib().clbm_batch_residual(self._h, int(i), out), "clbm_batch_residual")
         return out[0], out[1]
 
-    def set_launch(self, tile_x, tile_y, persistent_wgs=0, steps_per_launch=1):
-        L = clbm_batch_launch(int(tile_x), int(tile_y), int(persistent_wgs), int(steps_per_launch))
+    def set_launch(self, tile_x, tile_y, persistent_wgs=0, steps_per_launch=1, xcd_bands=1):
+        L = clbm_batch_launch(int(tile_x), int(tile_y), int(persistent_wgs), int(steps_per_launch),
+                              int(xcd_bands))
         _check(lib().clbm_batch_set_launch(self._h, ctypes.byref(L)), "clbm_batch_set_launch")
 
     def autotune(self, steps=20, cache_path=None):
@@ -462,8 +497,7 @@ class Batch:
         path = cache_path.encode() if cache_path else None
         _check(lib().clbm_batch_autotune(self._h, int(steps), path, ctypes.byref(best)),
                "clbm_batch_autotune")
-        return {"tile_x": best.tile_x, "tile_y": best.tile_y, "persistent_wgs": best.persistent_wgs,
-                "steps_per_launch": best.steps_per_launch}
+        return _launch_dict(best)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -28,7 +28,9 @@ constexpr int kBP = 6;  // per-tile partials: du2, u2, dT2, T2, bad, max|u|
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// One time step of every instance on the active tile list (grid-stride over tiles).
+// One time step of every instance on the active tile list (grid-stride over tiles); S is
+// the storage type of every instance's populations.
+template <typename S>
 __global__ void __launch_bounds__(1024) k_batch_step(const BatchInst* __restrict__ insts,
                                                      const int2* __restrict__ list,
                                                      const int* __restrict__ count, int parity,
@@ -42,21 +44,25 @@ __global__ void __launch_bounds__(1024) k_batch_step(const BatchInst* __restrict
         const LatticeConst c = I.c;
         const int tiles_x = uniform_int(I.tiles_x);
         const int x = (tile % tiles_x) * tile_x + threadIdx.x;
-        const int y = (tile / tiles_x) * tile_y + threadIdx.y;
+        // a tile taller than the block is covered by looping over its rows
+        for (int ly = threadIdx.y; ly < tile_y; ly += blockDim.y) {
+        const int y = (tile / tiles_x) * tile_y + ly;
         if (x < c.nx && y < c.ny) {
-            const float* src = reinterpret_cast<const float*>(I.buf[parity]);
-            float* dst = reinterpret_cast<float*>(I.buf[parity ^ 1]);
+            typedef typename Wide<S>::type W;
+            const S* src = reinterpret_cast<const S*>(I.buf[parity]);
+            S* dst = reinterpret_cast<S*>(I.buf[parity ^ 1]);
             float a[9], b[5];
-            double fa[9], tb[5];
+            W fa[9], tb[5];
             NodeMacro m;
             if (c.viscous) {
-                gather_node<float, true, unsigned>(src, c, x, y, a, b);
-                collide<float, true, double>(c, a, b, fa, tb, m);
+                gather_node<S, true, unsigned>(src, c, x, y, a, b);
+                collide<float, true, W>(c, a, b, fa, tb, m);
             } else {
-                gather_node<float, false, unsigned>(src, c, x, y, a, b);
-                collide<float, false, double>(c, a, b, fa, tb, m);
+                gather_node<S, false, unsigned>(src, c, x, y, a, b);
+                collide<float, false, W>(c, a, b, fa, tb, m);
             }
-            store_node<float, unsigned>(dst, c, x, y, fa, tb);
+            store_node<S, unsigned>(dst, c, x, y, fa, tb);
+        }
         }
     }
 }
@@ -77,24 +83,25 @@ __device__ __forceinline__ int banded_tile(int k, int n)
     return j < band && t < n ? t : n;
 }
 
-// Two time steps of every instance on the active tile list (tiles of kBlock x
-// kTwoStepRows nodes, grid-stride over tiles; the LDS tile is reused by each tile a
-// workgroup takes). Per tile it runs the phases of k_step2, so two steps here are two
-// steps of k_batch_step bit for bit. VH: 0 = no instance has viscous heating, 1 = all
-// have, 2 = mixed (both paths compiled in; the register budget is held at two
-// workgroups per CU).
-template <int VH>
-__global__ void __launch_bounds__(kTwoStepThreads) __attribute__((amdgpu_waves_per_eu(4))) k_batch_step2(const BatchInst* __restrict__ insts,
+// Two time steps of every instance on the active tile list (tiles of kBlock x TY nodes,
+// NT threads, grid-stride over tiles; the LDS tile is reused by each tile a workgroup
+// takes). Per tile it runs the phases of k_step2, so two steps here are two steps of
+// k_batch_step bit for bit. VH: 0 = no instance has viscous heating, 1 = all have, 2 =
+// mixed (both paths compiled in; the register budget is held at four waves per SIMD).
+// bands != 0 deals the list to the XCDs in contiguous bands (banded_tile), else every
+// workgroup strides over the whole list.
+template <typename S, int VH, int TY, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_batch_step2(const BatchInst* __restrict__ insts,
                                                                     const int2* __restrict__ list,
                                                                     const int* __restrict__ count,
-                                                                    int parity)
+                                                                    int parity, int bands)
 {
-    constexpr int TY = kTwoStepRows, NT = kTwoStepThreads;
-    __shared__ float tile[14 * Tile2<TY>::P];
+    __shared__ S tile[14 * Tile2<TY>::P];
     const int n = uniform_int(*count);
     const int tid = (int)threadIdx.x;
     for (int k = 0;; ++k) {
-        const int t = banded_tile(k, n);
+        int t = (int)blockIdx.x + k * (int)gridDim.x;
+        if (bands) t = banded_tile(k, n);
         if (t >= n) break;
         const int2 e = list[t];
         const int inst = uniform_int(e.x), id = uniform_int(e.y);
@@ -102,16 +109,16 @@ __global__ void __launch_bounds__(kTwoStepThreads) __attribute__((amdgpu_waves_p
         const LatticeConst c = I.c;
         const int tiles_x = uniform_int(I.tiles_x);
         const int X0 = (id % tiles_x) * (int)kBlock, Y0 = (id / tiles_x) * TY;
-        const float* src = reinterpret_cast<const float*>(I.buf[parity]);
-        float* dst = reinterpret_cast<float*>(I.buf[parity ^ 1]);
+        const S* src = reinterpret_cast<const S*>(I.buf[parity]);
+        S* dst = reinterpret_cast<S*>(I.buf[parity ^ 1]);
         if (VH == 1 || (VH == 2 && c.viscous)) {
-            step2_phase1<float, true, TY, NT, unsigned>(src, c, tile, X0, Y0, tid);
+            step2_phase1<S, true, TY, NT, unsigned>(src, c, tile, X0, Y0, tid);
             __syncthreads();
-            step2_phase2<float, true, TY, NT, unsigned>(dst, c, tile, X0, Y0, tid);
+            step2_phase2<S, true, TY, NT, unsigned>(dst, c, tile, X0, Y0, tid);
         } else {
-            step2_phase1<float, false, TY, NT, unsigned>(src, c, tile, X0, Y0, tid);
+            step2_phase1<S, false, TY, NT, unsigned>(src, c, tile, X0, Y0, tid);
             __syncthreads();
-            step2_phase2<float, false, TY, NT, unsigned>(dst, c, tile, X0, Y0, tid);
+            step2_phase2<S, false, TY, NT, unsigned>(dst, c, tile, X0, Y0, tid);
         }
         __syncthreads();  // the next tile overwrites the LDS tile
     }
@@ -135,6 +142,7 @@ __device__ __forceinline__ double wave_max_d(double v)
 // then the snapshot is replaced by the current fields. Partials go to the tile's
 // fixed slot (its index in the full list), so the per-instance sums are formed in a
 // fixed order by k_batch_finalize.
+template <typename S>
 __global__ void __launch_bounds__(1024) k_batch_diag(const BatchInst* __restrict__ insts,
                                                      const int2* __restrict__ list,
                                                      const int* __restrict__ count, int parity,
@@ -152,10 +160,12 @@ __global__ void __launch_bounds__(1024) k_batch_diag(const BatchInst* __restrict
         const LatticeConst c = I.c;
         const int tiles_x = uniform_int(I.tiles_x);
         const int x = (tile % tiles_x) * tile_x + threadIdx.x;
-        const int y = (tile / tiles_x) * tile_y + threadIdx.y;
         double acc[kBP] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        // a tile taller than the block is covered by looping over its rows
+        for (int ly = threadIdx.y; ly < tile_y; ly += blockDim.y) {
+        const int y = (tile / tiles_x) * tile_y + ly;
         if (x < c.nx && y < c.ny) {
-            const float* src = reinterpret_cast<const float*>(I.buf[parity]);
+            const S* src = reinterpret_cast<const S*>(I.buf[parity]);
             float* snap = reinterpret_cast<float*>(I.snap);
             float a[9], b[5];
             load_own(src, c, node_off(c, x, y), a, b);
@@ -165,17 +175,18 @@ __global__ void __launch_bounds__(1024) k_batch_diag(const BatchInst* __restrict
             const double u2 = (double)m.ux * m.ux + (double)m.uy * m.uy;
             if (compare) {
                 const double dx = m.ux - snap[k], dy = m.uy - snap[np + k], dt = T - snap[2 * np + k];
-                acc[0] = dx * dx + dy * dy;
-                acc[2] = dt * dt;
+                acc[0] += dx * dx + dy * dy;
+                acc[2] += dt * dt;
             }
-            acc[1] = u2;
-            acc[3] = (double)T * T;
+            acc[1] += u2;
+            acc[3] += (double)T * T;
             const bool ok = isfinite(m.drho) && isfinite(m.ux) && isfinite(m.uy) && isfinite(T);
-            acc[4] = ok ? 0.0 : 1.0;
-            acc[5] = ok ? sqrt(u2) : 1e30;
+            acc[4] += ok ? 0.0 : 1.0;
+            acc[5] = fmax(acc[5], ok ? sqrt(u2) : 1e30);
             snap[k] = m.ux;
             snap[np + k] = m.uy;
             snap[2 * np + k] = T;
+        }
         }
 #pragma unroll
         for (int q = 0; q < kBP; ++q) {
@@ -280,6 +291,15 @@ __global__ void __launch_bounds__(256) k_batch_scatter(const BatchInst* __restri
     active[newoff[e.x] + e.y] = e;
 }
 
+// Every instance on the active list (statuses and step counts unchanged).
+__global__ void k_batch_activate_all(const int2* __restrict__ full, int total, int2* __restrict__ active,
+                                     int* __restrict__ count)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < total) active[k] = full[k];
+    if (k == 0) *count = total;
+}
+
 __global__ void k_batch_reset(int* __restrict__ status, long long* __restrict__ steps,
                               double* __restrict__ res, int n, const int2* __restrict__ full,
                               int total, int2* __restrict__ active, int* __restrict__ count)
@@ -301,6 +321,7 @@ using namespace clbm;
 
 struct clbm_batch {
     int n;
+    int precision;   // storage of every instance: CLBM_FP32 or CLBM_FP16_SHIFTED
     std::vector<clbm_params> p;
     std::vector<BatchInst> inst;
     std::vector<int2> full_host;
@@ -338,10 +359,15 @@ struct BatchLayout {
     int cap_tiles;
 };
 
+// Tile heights of the two-step kernel (kBlock columns): rows + 2 halo rows are dealt to
+// the waves of the workgroup, so the thread count is 64 (rows + 2) / 2.
+bool two_step_rows_ok(int rows) { return rows == 6 || rows == kTwoStepRows || rows == 30; }
+int two_step_threads(int rows) { return rows == 6 ? 256 : rows == 30 ? 1024 : kTwoStepThreads; }
+
 bool batch_launch_ok(const clbm_batch_launch& L)
 {
-    if (L.persistent_wgs < 0) return false;
-    if (L.steps_per_launch == 2) return L.tile_x == (int)kBlock && L.tile_y == kTwoStepRows;
+    if (L.persistent_wgs < 0 || (L.xcd_bands != 0 && L.xcd_bands != 1)) return false;
+    if (L.steps_per_launch == 2) return L.tile_x == (int)kBlock && two_step_rows_ok(L.tile_y);
     if (L.steps_per_launch != 1) return false;
     return L.tile_x >= kMinTileX && L.tile_x % 64 == 0 && L.tile_y >= 1 && L.tile_x * L.tile_y <= 1024;
 }
@@ -353,6 +379,7 @@ clbm_batch_launch default_batch_launch()
     L.tile_y = kTwoStepRows;
     L.persistent_wgs = 0;
     L.steps_per_launch = 2;
+    L.xcd_bands = 1;
     return L;
 }
 
@@ -366,8 +393,11 @@ clbm_status batch_layout(int n, const clbm_params* p, BatchLayout* L)
         return o;
     };
     long long cap = 0;
+    // one storage type for the whole batch
+    if (p[0].precision != CLBM_FP32 && p[0].precision != CLBM_FP16_SHIFTED) return CLBM_ERR_UNSUPPORTED;
+    const size_t elem = p[0].precision == CLBM_FP16_SHIFTED ? 2 : 4;
     for (int i = 0; i < n; ++i) {
-        if (p[i].precision != CLBM_FP32) return CLBM_ERR_UNSUPPORTED;
+        if (p[i].precision != p[0].precision) return CLBM_ERR_UNSUPPORTED;
         clbm_status st = validate(&p[i], nullptr);
         if (st != CLBM_OK) return st;
         // the batched kernels address an instance with 32-bit element offsets
@@ -392,8 +422,8 @@ clbm_status batch_layout(int n, const clbm_params* p, BatchLayout* L)
     L->snap.resize(n);
     for (int i = 0; i < n; ++i) {
         const size_t elems = buffer_elems(p[i].nx, p[i].ny);
-        L->buf0[i] = take(elems * sizeof(float));
-        L->buf1[i] = take(elems * sizeof(float));
+        L->buf0[i] = take(elems * elem);
+        L->buf1[i] = take(elems * elem);
         L->snap[i] = take(3 * (size_t)p[i].nx * p[i].ny * sizeof(float));
     }
     L->total = off;
@@ -463,30 +493,64 @@ clbm_status add_node(hipGraph_t g, hipGraphNode_t* prev, const void* fn, dim3 gr
     return CLBM_OK;
 }
 
-// The two-step kernel for the batch's mix of instances with and without viscous heating.
+template <typename S, int VH>
+const void* step2_rows(int rows)
+{
+    if (rows == 6) return reinterpret_cast<const void*>(&k_batch_step2<S, VH, 6, 256>);
+    if (rows == 30) return reinterpret_cast<const void*>(&k_batch_step2<S, VH, 30, 1024>);
+    return reinterpret_cast<const void*>(&k_batch_step2<S, VH, kTwoStepRows, kTwoStepThreads>);
+}
+
+template <typename S>
+const void* step2_for(int vh, int rows)
+{
+    return vh == 0 ? step2_rows<S, 0>(rows) : vh == 1 ? step2_rows<S, 1>(rows) : step2_rows<S, 2>(rows);
+}
+
+// The two-step kernel for the batch's storage type, tile height and mix of instances with
+// and without viscous heating.
 const void* step2_kernel(const clbm_batch* b)
 {
     int vh = 0;
     for (int i = 0; i < b->n; ++i) vh += b->p[i].viscous_heating ? 1 : 0;
-    if (vh == 0) return reinterpret_cast<const void*>(&k_batch_step2<0>);
-    if (vh == b->n) return reinterpret_cast<const void*>(&k_batch_step2<1>);
-    return reinterpret_cast<const void*>(&k_batch_step2<2>);
+    const int mix = vh == 0 ? 0 : (vh == b->n ? 1 : 2);
+    return b->precision == CLBM_FP16_SHIFTED ? step2_for<__half>(mix, b->launch.tile_y)
+                                             : step2_for<float>(mix, b->launch.tile_y);
+}
+
+const void* step1_kernel(const clbm_batch* b)
+{
+    return b->precision == CLBM_FP16_SHIFTED ? reinterpret_cast<const void*>(&k_batch_step<__half>)
+                                             : reinterpret_cast<const void*>(&k_batch_step<float>);
+}
+
+const void* diag_kernel(const clbm_batch* b)
+{
+    return b->precision == CLBM_FP16_SHIFTED ? reinterpret_cast<const void*>(&k_batch_diag<__half>)
+                                             : reinterpret_cast<const void*>(&k_batch_diag<float>);
+}
+
+// Block shape of the one-step and diagnostics kernels (a two-step tile of kBlock x rows
+// nodes is covered by kBlock x min(rows, 16) threads, rows looped).
+dim3 tile_block(const clbm_batch* b)
+{
+    return dim3(b->launch.tile_x, std::min(b->launch.tile_y, 1024 / b->launch.tile_x));
 }
 
 clbm_status launch_batch_steps(clbm_batch* b, int nsteps)
 {
-    const dim3 blk(b->launch.tile_x, b->launch.tile_y);
     while (nsteps > 0) {
         if (b->launch.steps_per_launch == 2 && nsteps >= 2) {
-            int parity = b->parity;
-            void* args[] = {&b->d_inst, &b->d_active, &b->d_count, &parity};
-            CLBM_HIP(hipLaunchKernel(step2_kernel(b), step_grid(b), dim3(kTwoStepThreads), args, 0,
-                                     b->stream));
+            int parity = b->parity, bands = b->launch.xcd_bands;
+            void* args[] = {&b->d_inst, &b->d_active, &b->d_count, &parity, &bands};
+            CLBM_HIP(hipLaunchKernel(step2_kernel(b), step_grid(b), dim3(two_step_threads(b->launch.tile_y)),
+                                     args, 0, b->stream));
             b->step += 2;
             nsteps -= 2;
         } else {
-            hipLaunchKernelGGL(k_batch_step, step_grid(b), blk, 0, b->stream, b->d_inst, b->d_active,
-                               b->d_count, b->parity, b->launch.tile_x, b->launch.tile_y);
+            int parity = b->parity, tx = b->launch.tile_x, ty = b->launch.tile_y;
+            void* args[] = {&b->d_inst, &b->d_active, &b->d_count, &parity, &tx, &ty};
+            CLBM_HIP(hipLaunchKernel(step1_kernel(b), step_grid(b), tile_block(b), args, 0, b->stream));
             b->step += 1;
             nsteps -= 1;
         }
@@ -498,10 +562,9 @@ clbm_status launch_batch_steps(clbm_batch* b, int nsteps)
 
 clbm_status launch_diag(clbm_batch* b, int compare)
 {
-    const dim3 blk(b->launch.tile_x, b->launch.tile_y);
-    hipLaunchKernelGGL(k_batch_diag, step_grid(b), blk, 0, b->stream, b->d_inst, b->d_active,
-                       b->d_count, b->parity, b->launch.tile_x, b->launch.tile_y, compare, b->d_part);
-    CLBM_HIP(hipGetLastError());
+    int parity = b->parity, tx = b->launch.tile_x, ty = b->launch.tile_y;
+    void* args[] = {&b->d_inst, &b->d_active, &b->d_count, &parity, &tx, &ty, &compare, &b->d_part};
+    CLBM_HIP(hipLaunchKernel(diag_kernel(b), step_grid(b), tile_block(b), args, 0, b->stream));
     return CLBM_OK;
 }
 
@@ -512,9 +575,9 @@ clbm_status build_run_graph(clbm_batch* b, int K, double tol, long max_steps)
     hipGraph_t g = nullptr;
     CLBM_HIP(hipGraphCreate(&g, 0));
     hipGraphNode_t prev = nullptr;
-    const dim3 blk(b->launch.tile_x, b->launch.tile_y);
+    const dim3 blk = tile_block(b);
     const dim3 grid = step_grid(b);
-    int parity = b->parity;
+    int parity = b->parity, bands = b->launch.xcd_bands;
     int tx = b->launch.tile_x, ty = b->launch.tile_y;
     clbm_status st = CLBM_OK;
     // The graph is replayed from the same buffer, so it must flip the buffers an even
@@ -526,19 +589,19 @@ clbm_status build_run_graph(clbm_batch* b, int K, double tol, long max_steps)
         singles = K - 2 * pairs;
     }
     for (int k = 0; k < pairs && st == CLBM_OK; ++k) {
-        void* args[] = {&b->d_inst, &b->d_active, &b->d_count, &parity};
-        st = add_node(g, &prev, step2_kernel(b), grid, dim3(kTwoStepThreads), args);
+        void* args[] = {&b->d_inst, &b->d_active, &b->d_count, &parity, &bands};
+        st = add_node(g, &prev, step2_kernel(b), grid, dim3(two_step_threads(b->launch.tile_y)), args);
         parity ^= 1;
     }
     for (int k = 0; k < singles && st == CLBM_OK; ++k) {
         void* args[] = {&b->d_inst, &b->d_active, &b->d_count, &parity, &tx, &ty};
-        st = add_node(g, &prev, reinterpret_cast<const void*>(&k_batch_step), grid, blk, args);
+        st = add_node(g, &prev, step1_kernel(b), grid, blk, args);
         parity ^= 1;
     }
     int compare = 1;
     if (st == CLBM_OK) {
         void* args[] = {&b->d_inst, &b->d_active, &b->d_count, &parity, &tx, &ty, &compare, &b->d_part};
-        st = add_node(g, &prev, reinterpret_cast<const void*>(&k_batch_diag), grid, blk, args);
+        st = add_node(g, &prev, diag_kernel(b), grid, blk, args);
     }
     long long maxs = max_steps;
     if (st == CLBM_OK) {
@@ -576,6 +639,36 @@ clbm_status build_run_graph(clbm_batch* b, int K, double tol, long max_steps)
     return CLBM_OK;
 }
 
+// Workload signature of a batch for the tuning cache: FNV-1a (64-bit) over the instance
+// count, the storage type and each instance's (nx, ny, viscous heating), as 16 hex digits.
+void signature(const clbm_batch* b, char out[17])
+{
+    unsigned long long h = 0xcbf29ce484222325ull;
+    auto mix = [&](long long v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (unsigned long long)((v >> (8 * k)) & 0xff);
+            h *= 0x100000001b3ull;
+        }
+    };
+    mix(b->n);
+    mix(b->precision);
+    for (int i = 0; i < b->n; ++i) {
+        mix(b->p[i].nx);
+        mix(b->p[i].ny);
+        mix(b->p[i].viscous_heating ? 1 : 0);
+    }
+    std::snprintf(out, 17, "%016llx", h);
+}
+
+// Integer value of "name": in one line of the cache (the format autotune writes).
+bool json_int(const char* line, const char* name, int* v)
+{
+    char key[40];
+    std::snprintf(key, sizeof key, "\"%s\": ", name);
+    const char* p = std::strstr(line, key);
+    return p && std::sscanf(p + std::strlen(key), "%d", v) == 1;
+}
+
 }  // namespace
 
 extern "C" {
@@ -606,6 +699,7 @@ clbm_status clbm_batch_create(int n, const clbm_params* p, void* d_workspace, si
     if (!b) return CLBM_ERR_INVALID_ARG;
     char* ws = (char*)d_workspace;
     b->n = n;
+    b->precision = p[0].precision;
     b->p.assign(p, p + n);
     b->inst.resize(n);
     b->stream = (hipStream_t)hip_stream;
@@ -659,8 +753,12 @@ clbm_status clbm_batch_init(clbm_batch* b, int i, const float* d_rho, const floa
     const dim3 blk(64, 4);
     const dim3 grd = node_grid(I.c, blk);
     // the current buffer of the batch (all instances share the parity)
-    hipLaunchKernelGGL(k_init<float>, grd, blk, 0, b->stream, (float*)(uintptr_t)I.buf[b->parity],
-                       I.c, d_rho, d_ux, d_uy, d_T);
+    if (b->precision == CLBM_FP16_SHIFTED)
+        hipLaunchKernelGGL(k_init<__half>, grd, blk, 0, b->stream, (__half*)(uintptr_t)I.buf[b->parity],
+                           I.c, d_rho, d_ux, d_uy, d_T);
+    else
+        hipLaunchKernelGGL(k_init<float>, grd, blk, 0, b->stream, (float*)(uintptr_t)I.buf[b->parity],
+                           I.c, d_rho, d_ux, d_uy, d_T);
     CLBM_HIP(hipGetLastError());
     return CLBM_OK;
 }
@@ -668,7 +766,23 @@ clbm_status clbm_batch_init(clbm_batch* b, int i, const float* d_rho, const floa
 clbm_status clbm_batch_step(clbm_batch* b, int nsteps)
 {
     if (!b || nsteps < 0) return CLBM_ERR_INVALID_ARG;
-    return launch_batch_steps(b, nsteps);
+    if (nsteps == 0) return CLBM_OK;
+    // Every instance advances, the ones a run has retired included: all instances share
+    // the buffer parity, which flips with every launch. The active list is widened to
+    // the full list for these steps and rebuilt from the run's statuses afterwards.
+    hipLaunchKernelGGL(k_batch_activate_all, dim3((b->total_tiles + 255) / 256), dim3(256), 0, b->stream,
+                       b->d_full, b->total_tiles, b->d_active, b->d_count);
+    CLBM_HIP(hipGetLastError());
+    clbm_status st = launch_batch_steps(b, nsteps);
+    if (st != CLBM_OK) return st;
+    int n = b->n, total = b->total_tiles;
+    hipLaunchKernelGGL(k_batch_scan, dim3(1), dim3(1024), 0, b->stream, b->d_inst, b->d_status, n,
+                       b->d_newoff, b->d_count);
+    CLBM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_batch_scatter, dim3((total + 255) / 256), dim3(256), 0, b->stream, b->d_inst,
+                       b->d_status, b->d_newoff, b->d_full, total, b->d_active);
+    CLBM_HIP(hipGetLastError());
+    return CLBM_OK;
 }
 
 clbm_status clbm_batch_reset(clbm_batch* b)
@@ -720,8 +834,12 @@ clbm_status clbm_batch_macros(clbm_batch* b, int i, float* d_rho, float* d_ux, f
     const BatchInst& I = b->inst[i];
     const dim3 blk(64, 4);
     const dim3 grd = node_grid(I.c, blk);
-    hipLaunchKernelGGL(k_macros<float>, grd, blk, 0, b->stream,
-                       (const float*)(uintptr_t)I.buf[b->parity], I.c, d_rho, d_ux, d_uy, d_T);
+    if (b->precision == CLBM_FP16_SHIFTED)
+        hipLaunchKernelGGL(k_macros<__half>, grd, blk, 0, b->stream,
+                           (const __half*)(uintptr_t)I.buf[b->parity], I.c, d_rho, d_ux, d_uy, d_T);
+    else
+        hipLaunchKernelGGL(k_macros<float>, grd, blk, 0, b->stream,
+                           (const float*)(uintptr_t)I.buf[b->parity], I.c, d_rho, d_ux, d_uy, d_T);
     CLBM_HIP(hipGetLastError());
     return CLBM_OK;
 }
@@ -732,9 +850,14 @@ clbm_status clbm_batch_diagnostics(clbm_batch* b, int i, clbm_diag* out)
     const BatchInst& I = b->inst[i];
     const size_t n = (size_t)I.c.nx * I.c.ny;
     const int blocks = (int)std::min<size_t>((n + kDiagBlock - 1) / kDiagBlock, kDiagMaxBlocks);
-    hipLaunchKernelGGL(k_diag<float>, dim3(blocks), dim3(kDiagBlock), 0, b->stream,
-                       (const float*)(uintptr_t)I.buf[b->parity], I.c, (float*)(uintptr_t)I.snap, 0,
-                       b->d_dpart);
+    if (b->precision == CLBM_FP16_SHIFTED)
+        hipLaunchKernelGGL(k_diag<__half>, dim3(blocks), dim3(kDiagBlock), 0, b->stream,
+                           (const __half*)(uintptr_t)I.buf[b->parity], I.c, (float*)(uintptr_t)I.snap, 0,
+                           b->d_dpart);
+    else
+        hipLaunchKernelGGL(k_diag<float>, dim3(blocks), dim3(kDiagBlock), 0, b->stream,
+                           (const float*)(uintptr_t)I.buf[b->parity], I.c, (float*)(uintptr_t)I.snap, 0,
+                           b->d_dpart);
     CLBM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, b->stream, b->d_dpart, blocks, b->d_dres);
     CLBM_HIP(hipGetLastError());
@@ -779,11 +902,14 @@ clbm_status clbm_batch_autotune(clbm_batch* b, int steps, const char* cache_path
                                 clbm_batch_launch* best)
 {
     if (!b || steps < 1) return CLBM_ERR_INVALID_ARG;
-    // {tile_x, tile_y, steps per launch}
+    // {tile_x, tile_y, steps per launch}: one-step tiles, then the two-step tile heights
     static const int shapes[][3] = {{64, 1, 1}, {64, 2, 1}, {64, 4, 1}, {64, 8, 1}, {128, 1, 1},
                                     {128, 2, 1}, {128, 4, 1}, {256, 1, 1}, {256, 2, 1}, {256, 4, 1},
-                                    {512, 1, 1}, {512, 2, 1}, {(int)kBlock, kTwoStepRows, 2}};
+                                    {512, 1, 1}, {512, 2, 1}, {(int)kBlock, 6, 2},
+                                    {(int)kBlock, kTwoStepRows, 2}, {(int)kBlock, 30, 2}};
     static const int wgs[] = {0, 2048, 8192};
+    char sig[17];
+    signature(b, sig);
     FILE* fp = cache_path ? std::fopen(cache_path, "a") : nullptr;
     hipEvent_t e0, e1;
     CLBM_HIP(hipEventCreate(&e0));
@@ -794,49 +920,86 @@ clbm_status clbm_batch_autotune(clbm_batch* b, int steps, const char* cache_path
     for (int i = 0; i < b->n; ++i) nodes += (long long)b->p[i].nx * b->p[i].ny;
     clbm_status st = CLBM_OK;
     for (const auto& sh : shapes) {
-        for (int w : wgs) {
-            clbm_batch_launch L;
-            L.tile_x = sh[0];
-            L.tile_y = sh[1];
-            L.steps_per_launch = sh[2];
-            L.persistent_wgs = w;
-            if (!batch_launch_ok(L)) continue;
-            b->launch = L;
-            st = apply_shape(b);
-            if (st != CLBM_OK) break;
-            if (w > 0 && w >= b->total_tiles) continue;  // same as one workgroup per tile
-            st = launch_batch_steps(b, 2);               // warm-up (even: parity unchanged)
-            if (st != CLBM_OK) break;
-            CLBM_HIP(hipEventRecord(e0, b->stream));
-            st = launch_batch_steps(b, 2 * ((steps + 1) / 2));
-            if (st != CLBM_OK) break;
-            CLBM_HIP(hipEventRecord(e1, b->stream));
-            CLBM_HIP(hipEventSynchronize(e1));
-            float ms = 0.f;
-            CLBM_HIP(hipEventElapsedTime(&ms, e0, e1));
-            const double per = ms / (2 * ((steps + 1) / 2));
-            if (fp)
-                std::fprintf(fp, "{\"tile_x\": %d, \"tile_y\": %d, \"persistent_wgs\": %d, "
-                                 "\"steps_per_launch\": %d, "
-                                 "\"instances\": %d, \"nodes\": %lld, \"ms_per_step\": %.6f, "
-                                 "\"mlups\": %.1f}\n",
-                             L.tile_x, L.tile_y, L.persistent_wgs, L.steps_per_launch, b->n, nodes, per,
-                             nodes / (per * 1e-3) / 1e6);
-            if (per < best_ms) {
-                best_ms = per;
-                best_L = L;
+        for (int bands = 0; bands < (sh[2] == 2 ? 2 : 1); ++bands) {
+            for (int w : wgs) {
+                clbm_batch_launch L;
+                L.tile_x = sh[0];
+                L.tile_y = sh[1];
+                L.steps_per_launch = sh[2];
+                L.persistent_wgs = w;
+                L.xcd_bands = sh[2] == 2 ? bands : 0;
+                if (!batch_launch_ok(L)) continue;
+                b->launch = L;
+                st = apply_shape(b);
+                if (st != CLBM_OK) break;
+                if (w > 0 && w >= b->total_tiles) continue;  // same as one workgroup per tile
+                st = launch_batch_steps(b, 2);               // warm-up
+                if (st != CLBM_OK) break;
+                CLBM_HIP(hipEventRecord(e0, b->stream));
+                st = launch_batch_steps(b, 2 * ((steps + 1) / 2));
+                if (st != CLBM_OK) break;
+                CLBM_HIP(hipEventRecord(e1, b->stream));
+                CLBM_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                CLBM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                const double per = ms / (2 * ((steps + 1) / 2));
+                if (fp)
+                    std::fprintf(fp, "{\"signature\": \"%s\", \"tile_x\": %d, \"tile_y\": %d, "
+                                     "\"persistent_wgs\": %d, \"steps_per_launch\": %d, \"xcd_bands\": %d, "
+                                     "\"instances\": %d, \"nodes\": %lld, \"ms_per_step\": %.6f, "
+                                     "\"mlups\": %.1f}\n",
+                                 sig, L.tile_x, L.tile_y, L.persistent_wgs, L.steps_per_launch, L.xcd_bands,
+                                 b->n, nodes, per, nodes / (per * 1e-3) / 1e6);
+                if (per < best_ms) {
+                    best_ms = per;
+                    best_L = L;
+                }
             }
+            if (st != CLBM_OK) break;
         }
         if (st != CLBM_OK) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (fp && st == CLBM_OK)
+        std::fprintf(fp, "{\"signature\": \"%s\", \"best\": 1, \"tile_x\": %d, \"tile_y\": %d, "
+                         "\"persistent_wgs\": %d, \"steps_per_launch\": %d, \"xcd_bands\": %d, "
+                         "\"ms_per_step\": %.6f}\n",
+                     sig, best_L.tile_x, best_L.tile_y, best_L.persistent_wgs, best_L.steps_per_launch,
+                     best_L.xcd_bands, best_ms);
     if (fp) std::fclose(fp);
     b->launch = best_L;
     clbm_status st2 = apply_shape(b);
     if (st != CLBM_OK) return st;
     if (best) *best = best_L;
     return st2;
+}
+
+clbm_status clbm_batch_tune_lookup(const clbm_batch* b, const char* cache_path, clbm_batch_launch* out,
+                                   int* found)
+{
+    if (!b || !cache_path || !out || !found) return CLBM_ERR_INVALID_ARG;
+    *found = 0;
+    char sig[17];
+    signature(b, sig);
+    FILE* fp = std::fopen(cache_path, "r");
+    if (!fp) return CLBM_OK;
+    char line[1024];
+    char key[48];
+    std::snprintf(key, sizeof key, "\"signature\": \"%s\"", sig);
+    while (std::fgets(line, sizeof line, fp)) {
+        if (!std::strstr(line, key) || !std::strstr(line, "\"best\": 1")) continue;
+        clbm_batch_launch L;
+        if (json_int(line, "tile_x", &L.tile_x) && json_int(line, "tile_y", &L.tile_y) &&
+            json_int(line, "persistent_wgs", &L.persistent_wgs) &&
+            json_int(line, "steps_per_launch", &L.steps_per_launch) && json_int(line, "xcd_bands", &L.xcd_bands) &&
+            batch_launch_ok(L)) {
+            *out = L;  // the last matching line wins
+            *found = 1;
+        }
+    }
+    std::fclose(fp);
+    return CLBM_OK;
 }
 
 }  // extern "C"

@@ -226,9 +226,16 @@ static StepLaunch plan_step(const LatticeConst& c, int precision, const clbm_lau
     return s;
 }
 
+// Tile heights of the two-step kernel and their thread counts (rows + 2 halo rows dealt to
+// the waves: 64 (rows + 2) / 2 threads).
+static bool two_step_rows_ok(int rows) { return rows == 6 || rows == kTwoStepRows || rows == 30; }
+static int two_step_threads(int rows) { return rows == 6 ? 256 : rows == 30 ? 1024 : kTwoStepThreads; }
+
 static bool launch_ok(const clbm_launch& L, int precision)
 {
-    if (L.steps_per_launch == 2) return precision == CLBM_FP32 || precision == CLBM_FP16_SHIFTED;
+    if (L.steps_per_launch == 2)
+        return (precision == CLBM_FP32 || precision == CLBM_FP16_SHIFTED) &&
+               (L.two_step_rows == 0 || two_step_rows_ok(L.two_step_rows));
     if (L.steps_per_launch != 1) return false;
     const int threads = L.block_x * L.block_y;
     if (L.block_x < 1 || L.block_y < 1 || threads % 64 != 0 || threads > 1024) return false;
@@ -244,6 +251,7 @@ static clbm_launch default_single_launch()
     L.rows_per_thread = 1;
     L.xcd_remap = 0;
     L.steps_per_launch = 1;
+    L.two_step_rows = 0;
     return L;
 }
 
@@ -274,20 +282,28 @@ static const void* step2_fn(bool viscous, bool wide)
                    : reinterpret_cast<const void*>(&k_step2<S, false, TY, NT, unsigned>);
 }
 
+template <typename S>
+static const void* step2_for_rows(int rows, bool viscous, bool wide)
+{
+    if (rows == 6) return step2_fn<S, 6, 256>(viscous, wide);
+    if (rows == 30) return step2_fn<S, 30, 1024>(viscous, wide);
+    return step2_fn<S, kTwoStepRows, kTwoStepThreads>(viscous, wide);
+}
+
 static Step2Launch plan_step2(const LatticeConst& c, int precision, const clbm_launch& L)
 {
     Step2Launch s;
     const bool f16 = precision == CLBM_FP16_SHIFTED;
-    const int rows = f16 ? kTwoStepRowsF16 : kTwoStepRows;
-    s.fn = f16 ? step2_fn<__half, kTwoStepRowsF16, kTwoStepThreadsF16>(c.viscous != 0, wide_offsets(c))
-               : step2_fn<float, kTwoStepRows, kTwoStepThreads>(c.viscous != 0, wide_offsets(c));
+    const int rows = L.two_step_rows ? L.two_step_rows : (f16 ? kTwoStepRowsF16 : kTwoStepRows);
+    s.fn = f16 ? step2_for_rows<__half>(rows, c.viscous != 0, wide_offsets(c))
+               : step2_for_rows<float>(rows, c.viscous != 0, wide_offsets(c));
     s.tiles_x = (c.nx + (int)kBlock - 1) / (int)kBlock;
     const int tiles_y = (c.ny + rows - 1) / rows;
     s.tiles_total = s.tiles_x * tiles_y;
     s.remap = L.xcd_remap ? 1 : 0;
     const int g = s.remap ? (int)align_up((size_t)s.tiles_total, 8) : s.tiles_total;
     s.grid = dim3((unsigned)g, 1, 1);
-    s.block = dim3(f16 ? kTwoStepThreadsF16 : kTwoStepThreads, 1, 1);
+    s.block = dim3(two_step_threads(rows), 1, 1);
     return s;
 }
 

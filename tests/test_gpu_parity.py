@@ -315,3 +315,20 @@ def test_interior_blocks_fp16(kind):
     for r in runs[1:]:
         for x, y in zip(runs[0].populations(), r.populations()):
             assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("rows", [6, 30])
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("case", ["seed3", "walls", "periodic", "viscous"])
+def test_two_step_tile_heights(rows, precision, case):
+    """Two-step tiles of 64 x 6 and 64 x 30 nodes (256 and 1024 threads) give the state of
+    one-step launches bit for bit, for both storage types, at walls, in interior tiles, in
+    a fully periodic lattice and with viscous heating; 37 steps end with a one-step launch."""
+    import torch
+    prob, fields = random_case(int(case[4:])) if case.startswith("seed") else _interior_case(case)
+    a = run_gpu(prob, 37, fields, precision=precision, launch=dict(block_x=256, steps_per_launch=1))
+    b = run_gpu(prob, 37, fields, precision=precision,
+                launch=dict(steps_per_launch=2, xcd_remap=1, two_step_rows=rows))
+    assert b.get_launch()["two_step_rows"] == rows
+    for x, y in zip(a.populations(), b.populations()):
+        assert torch.equal(x, y), (rows, precision, case)

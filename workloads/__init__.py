@@ -186,7 +186,9 @@ def sweep(count=256, seed=2024, sides=SWEEP_SIDES, ra_range=(1e3, 1e6), pr_range
     """Seeded list of (problem, seed) pairs. Sides a <= b <= 2a drawn from `sides`,
     orientation by coin flip; Ra log-uniform, Pr and Q uniform. Where the U = 0.1 rule
     would give a relaxation time above tau_max the characteristic velocity is lowered
-    so that nu = (tau_max - 1/2)/3."""
+    so that nu = (tau_max - 1/2)/3. meta["under_resolved"] marks the instances whose
+    shear relaxation time tau_nu = 3 nu + 1/2 is below 0.52 (thin boundary layers at
+    high Ra on small grids; flagged, not changed)."""
     u = uniform01(seed, count * 8).reshape(count, 8)
     pairs = [(a, b) for a in sides for b in sides if a <= b <= 2 * a]
     out = []
@@ -202,7 +204,8 @@ def sweep(count=256, seed=2024, sides=SWEEP_SIDES, ra_range=(1e3, 1e6), pr_range
         if nu > nu_max:
             Uk = U * nu_max / nu
         prob = cavity(nx, ny, Ra=Ra, Pr=Pr, Q=Q, U=Uk)
-        prob["meta"] = {"Ra": Ra, "Pr": Pr, "U": Uk}
+        tau_nu = 3.0 * prob["nu"] + 0.5
+        prob["meta"] = {"Ra": Ra, "Pr": Pr, "U": Uk, "tau_nu": tau_nu, "under_resolved": tau_nu < 0.52}
         out.append((prob, int(seed * 1000 + k)))
     return out
 
