@@ -9,7 +9,8 @@ The arithmetic lives in ``clbm_oracle.c`` (literal dense matrices of Eq. (6),
 module only marshals numpy arrays through ctypes.
 
 Problem description: a plain dict with keys ``nx, ny, nu, alpha, g_beta, T0,
-Fx, Fy, Q`` (floats), optional rate overrides ``s_b, s_4, s_3, lambda_0,
+Fx, Fy, Q`` (floats), an optional source field ``Q_field`` ([ny][nx], added to
+Q per node), optional rate overrides ``s_b, s_4, s_3, lambda_0,
 lambda_2`` (None means the paper's default or rule) and ``sides``: four dicts
 (order x-, x+, y-, y+) with ``kind`` ("periodic" or "wall"), ``u_wall`` and
 the Robin data ``b1, b2, b3`` of ``b1 dT/dn + b2 T = b3`` (n outward).
@@ -38,6 +39,7 @@ class _Params(ctypes.Structure):
         ("viscous_heating", ctypes.c_int),
         ("kind", ctypes.c_int * 4), ("u_wall", ctypes.c_double * 4),
         ("b1", ctypes.c_double * 4), ("b2", ctypes.c_double * 4), ("b3", ctypes.c_double * 4),
+        ("Q_field", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -125,6 +127,16 @@ def make_params(prob):
     return p
 
 
+def _source_field(prob):
+    """The problem's per-node source field as a contiguous float64 [ny][nx] array, or None."""
+    q = prob.get("Q_field")
+    if q is None:
+        return None
+    q = np.ascontiguousarray(np.broadcast_to(np.asarray(q, dtype=np.float64),
+                                             (int(prob["ny"]), int(prob["nx"]))))
+    return q
+
+
 def rates(prob):
     """(s_nu, s_b, s_3, s_4, lambda_0, lambda_1, lambda_2) the oracle uses."""
     out = np.zeros(7)
@@ -203,6 +215,10 @@ class Sim:
         self.nx, self.ny = int(prob["nx"]), int(prob["ny"])
         self.nthreads = nthreads or default_threads()
         self._p = make_params(prob)
+        # the source field stays referenced for the life of the simulation
+        self._qfield = _source_field(prob)
+        if self._qfield is not None:
+            self._p.Q_field = _ptr(self._qfield)
         h = ctypes.c_void_p()
         _check(lib().oracle_create(ctypes.byref(self._p), ctypes.byref(h)), "oracle_create")
         self._h = h

@@ -294,11 +294,13 @@ static double dissipation(const oracle_params* p, const collide_ctx* c, const do
     return p->nu * (shear * shear + normal * normal);
 }
 
-/* Heat source at a node: the uniform Q plus, with viscous heating, the dissipation
- * evaluated from the pre-collision populations f (velocity from Eq. 12 with F = F_v). */
-static double local_source(const oracle_params* p, const collide_ctx* c, const double* f)
+/* Heat source at node k: the uniform Q, plus the caller's source field at k when there is
+ * one (k < 0: none), plus, with viscous heating, the dissipation evaluated from the
+ * pre-collision populations f (velocity from Eq. 12 with F = F_v). */
+static double local_source(const oracle_params* p, const collide_ctx* c, const double* f, long k)
 {
-    if (!p->viscous_heating) return p->Q;
+    const double Q = p->Q + ((p->Q_field && k >= 0) ? p->Q_field[k] : 0.0);
+    if (!p->viscous_heating) return Q;
     double rho = 0.0, jx = 0.0, jy = 0.0;
     for (int i = 0; i < Q9; ++i) {
         rho += f[i];
@@ -310,14 +312,14 @@ static double local_source(const oracle_params* p, const collide_ctx* c, const d
     oracle_matrix_N(ux, uy, N);
     matvec(Q9, c->M, f, raw);
     matvec(Q9, N, raw, cen);
-    return p->Q + dissipation(p, c, cen, rho);
+    return Q + dissipation(p, c, cen, rho);
 }
 
-static void collide_node(const oracle_params* p, const collide_ctx* c, const double* f,
+static void collide_node(const oracle_params* p, const collide_ctx* c, long k, const double* f,
                          const double* g, double* fp, double* gp, double* macro)
 {
     /* Eq. (25): temperature with the source correction. */
-    const double Qn = local_source(p, c, f);
+    const double Qn = local_source(p, c, f, k);
     double T = 0.0;
     for (int i = 0; i < Q5; ++i) T += g[i];
     T += 0.5 * Qn;
@@ -389,7 +391,7 @@ int oracle_collide(const oracle_params* p, const double f[9], const double g[5],
     collide_ctx c;
     int st = make_ctx(p, &c);
     if (st != ORACLE_OK) return st;
-    collide_node(p, &c, f, g, f_post, g_post, macro_out);
+    collide_node(p, &c, -1, f, g, f_post, g_post, macro_out);
     return ORACLE_OK;
 }
 
@@ -531,7 +533,7 @@ static void collide_all(const oracle_sim* s, const double* f, const double* g, d
         for (int x = 0; x < nx; ++x) {
             size_t k = (size_t)y * nx + x;
             double m[4];
-            collide_node(&s->p, &s->c, f + k * Q9, g + k * Q5, fp + k * Q9, gp + k * Q5, m);
+            collide_node(&s->p, &s->c, (long)k, f + k * Q9, g + k * Q5, fp + k * Q9, gp + k * Q5, m);
             if (rho) rho[k] = m[0];
             if (T) T[k] = m[3];
         }
@@ -603,7 +605,7 @@ int oracle_macros(const oracle_sim* s, double* rho, double* ux, double* uy, doub
         const double* g = s->g + k * Q5;
         double t = 0.0;
         for (int i = 0; i < Q5; ++i) t += g[i];
-        t += 0.5 * local_source(p, &s->c, f);              /* Eq. (25) */
+        t += 0.5 * local_source(p, &s->c, f, (long)k);     /* Eq. (25) */
         double Fx = p->Fx, Fy = p->Fy + p->g_beta * (t - p->T0); /* Eq. (2) */
         double r = 0.0, jx = 0.0, jy = 0.0;
         for (int i = 0; i < Q9; ++i) {

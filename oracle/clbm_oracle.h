@@ -52,6 +52,9 @@ typedef struct {
     int kind[4];      /* ORACLE_PERIODIC or ORACLE_WALL per side */
     double u_wall[4]; /* tangential speed of a moving wall (x- and x+: along y; y-, y+: along x) */
     double b1[4], b2[4], b3[4]; /* thermal wall data: b1 dT/dn + b2 T = b3, n outward */
+    const double* Q_field; /* NULL, or a heat source per node [ny][nx] added to Q (Sec. 3.2,
+                              a spatially variable source); read by the lattice calls, not
+                              by oracle_collide; the caller keeps it alive */
 } oracle_params;
 
 typedef struct oracle_sim oracle_sim;

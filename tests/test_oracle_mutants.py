@@ -20,7 +20,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE = os.path.join(ROOT, "oracle")
 PINS = ["tests/test_oracle_matrices.py", "tests/test_oracle_collision.py",
         "tests/test_oracle_relaxation.py", "tests/test_oracle_analytic.py",
-        "tests/test_oracle_viscous.py"]
+        "tests/test_oracle_viscous.py", "tests/test_oracle_source_field.py"]
 
 # (what the mistake is, original snippet, mutated snippet)
 MUTANTS = [
@@ -104,6 +104,12 @@ MUTANTS = [
      "double T2 = s->T[(size_t)y2 * nx + x2];", "double T2 = s->T[k];"),
     ("Sec. 3.2: factor 2 of the normal strain dropped",
      "(cen[3] - cen[4]) / (2.0 * CS2 * rho);", "(cen[3] - cen[4]) / (CS2 * rho);"),
+    ("source field ignored",
+     "((p->Q_field && k >= 0) ? p->Q_field[k] : 0.0)", "0.0"),
+    ("source field read at the previous node",
+     "((p->Q_field && k >= 0) ? p->Q_field[k] : 0.0)", "((p->Q_field && k >= 0) ? p->Q_field[k > 0 ? k - 1 : k] : 0.0)"),
+    ("source field counted twice",
+     "((p->Q_field && k >= 0) ? p->Q_field[k] : 0.0)", "((p->Q_field && k >= 0) ? 2.0 * p->Q_field[k] : 0.0)"),
     ("Sec. 3.2: shear strain rate halved",
      "double shear = -c->s_nu * cen[5] / (CS2 * rho);", "double shear = -c->s_nu * cen[5] / (CS2 * rho) * 0.5;"),
 ]
