@@ -603,6 +603,66 @@ def write_batch_summary(cache, res, out):
         fh.write("\n".join(lines) + "\n")
 
 
+def write_ws_summary(res, out, command):
+    """Markdown summary of a warm-start experiment (the JSON that --ws-out writes)."""
+    e = res["eval"]
+    lines = ["# Learned warm start: %d training steady states, %d held-out %d^2 cavities"
+             % (res.get("train_states", 0), e["cavities"], e["side"]), "",
+             "Workload: cavities with Ra log-uniform in [1e3, 1e6], Pr uniform in [0.7, 7], Q* = Q H^2/(alpha dT) "
+             "uniform in [0, 4]; training sides {64, 96, 128} (a <= b <= 2a, seed 2024), held-out square cavities "
+             "(seed 7). Network: 4-level conv encoder-decoder (32/64/128/256 channels, 15 3x3 convolutions) on a "
+             "%d^2 grid, BF16 MFMA with FP32 accumulation, trained by the library's kernels (Adam); its prediction is "
+             "resampled bilinearly and becomes the equilibrium initial state. Cold start: T0 + 1e-4 seeded noise at "
+             "rest. Both starts run in one batch each to residual 1e-7 (r = ||x^n - x^(n-K)|| / (K ||x^n||), K = 1000)"
+             "%s." % (res["grid"], ", then continue to %.0e" % e["refine"]["tol"] if "refine" in e else ""), "",
+             "Command (on the MI355X, where /root/repo is the repository):", "", "    cd /root/repo && " + command, ""]
+    if "train_states" in res:
+        lines += ["## Training", "", "| quantity | value |", "|---|---|",
+                  "| steady states generated (batched solver, cold start to 1e-7) | %d of %d in %.1f s (%.0f MLUPS) |"
+                  % (res["train_states"], res["train_requested"], res["generate_seconds"], res["generate_mlups"]),
+                  "| Adam steps x batch | %d x %d in %.1f s |" % (res["train_steps"], res["train_batch"],
+                                                                  res["train_seconds"]),
+                  "| network throughput (forward + backward, algorithmic flops) | %.2f TFLOP/s |" % res["train_tflops"],
+                  "| MSE loss, first 50 / last 50 steps | %.4f / %.6f |" % (res["loss_first"], res["loss_last"]), ""]
+    lines += ["## Held-out cavities: steps to residual 1e-7", "", "| quantity | value |", "|---|---|",
+              "| cavities, both converged | %d, %d |" % (e["cavities"], e["both_converged"]),
+              "| total steps cold / warm | %d / %d |" % (e["cold_steps_total"], e["warm_steps_total"]),
+              "| warm / cold steps (total, median per cavity) | %s, %s |" % (e["steps_ratio_warm_over_cold"],
+                                                                          e["median_ratio"]),
+              "| wall time cold / warm (s), batched solver | %s / %s |" % (e["cold_seconds"], e["warm_seconds"]),
+              "| Nu, warm vs cold at 1e-7: max / mean relative difference | %.2e / %.2e |"
+              % (e["nu_rel_diff_max"], e["nu_rel_diff_mean"]), ""]
+    if "refine" in e:
+        r = e["refine"]
+        lines += ["## Both runs continued to residual %.0e" % r["tol"], "", "| quantity | value |", "|---|---|",
+                  "| Nu, warm vs cold at %.0e: max relative difference | %.2e (%d of %d within 1e-3) |"
+                  % (r["tol"], r["nu_rel_diff_max"], r["nu_within_1e-3"], r["both_converged"]),
+                  "| Nu at 1e-7 vs the steady Nu (cold at %.0e): warm max / cold max | %.2e / %.2e |"
+                  % (r["tol"], r["warm_at_1e-7_vs_steady_max"], r["cold_at_1e-7_vs_steady_max"]),
+                  "| cavities whose Nu at 1e-7 is within 1e-3 of steady: warm / cold | %d / %d |"
+                  % (r["warm_at_1e-7_within_1e-3_of_steady"], r["cold_at_1e-7_within_1e-3_of_steady"]),
+                  "| total steps to %.0e: cold / warm (ratio) | %d / %d (%s) |"
+                  % (r["tol"], r["cold_steps_to_tol_total"], r["warm_steps_to_tol_total"], r["steps_ratio_to_tol"]),
+                  "| total steps until Nu stays within 1e-3 of steady: cold / warm (ratio; median per cavity) | "
+                  "%d / %d (%s; %s), %d cavities, Nu read every %d steps |"
+                  % (r["cold_steps_to_nu_1e-3_total"], r["warm_steps_to_nu_1e-3_total"], r["steps_ratio_to_nu_1e-3"],
+                     r["median_ratio_to_nu_1e-3"], r["nu_settled_both"], r["nu_settle_chunk_steps"]),
+                  "| wall time of the continuation cold / warm (s) | %s / %s |" % (r["cold_seconds"], r["warm_seconds"]),
+                  ""]
+    lines += ["## Per cavity", "",
+              "| Ra | Pr | Q* | cold steps | warm steps | warm/cold | Nu cold 1e-7 | Nu warm 1e-7 | Nu cold 1e-9 | "
+              "Nu warm 1e-9 | cold steps to Nu | warm steps to Nu |", "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for q in e["per_instance"]:
+        lines.append("| %.2e | %.2f | %.2f | %d | %d | %.2f | %.5f | %.5f | %s | %s | %s | %s |"
+                     % (q["Ra"], q["Pr"], q["Qstar"], q["cold_steps"], q["warm_steps"],
+                        q["warm_steps"] / max(q["cold_steps"], 1), q["cold_nu"], q["warm_nu"],
+                        "%.5f" % q["cold_refined_nu"] if "cold_refined_nu" in q else "-",
+                        "%.5f" % q["warm_refined_nu"] if "warm_refined_nu" in q else "-",
+                        q.get("cold_steps_to_nu", "-"), q.get("warm_steps_to_nu", "-")))
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def net_flops_per_sample(H, W, cin=8, cout=3, widths=(32, 64, 128, 256)):
     """Multiply-add flops of one forward pass of the warm-start network (3x3 convolutions)."""
     w1, w2, w3, w4 = widths
@@ -915,6 +975,7 @@ def main():
     ap.add_argument("--ws-refine-tol", type=float, default=0.0,
                     help="after the runs to 1e-7, continue both to this residual and compare Nu there")
     ap.add_argument("--ws-out", default="")
+    ap.add_argument("--ws-summary", default="", help="write the warm-start summary (markdown)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -946,6 +1007,8 @@ def main():
         if args.ws_out:
             with open(args.ws_out, "w") as fh:
                 json.dump(r, fh, indent=1)
+        if args.ws_summary:
+            write_ws_summary(r, args.ws_summary, " ".join(["python", "bench.py"] + sys.argv[1:]))
         print(json.dumps({"metric": METRIC, "warmstart": {k: v for k, v in r.items() if k != "eval"},
                           "eval": {k: v for k, v in r["eval"].items() if k != "per_instance"}}), flush=True)
         return
