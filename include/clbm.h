@@ -169,11 +169,19 @@ void clbm_destroy(clbm_handle* h);
 clbm_status clbm_init_from_fields(clbm_handle* h, const float* d_rho, const float* d_ux,
                                   const float* d_uy, const float* d_T);
 
-/* Advances nsteps time steps (one fused kernel per step; steps are replayed from
- * a HIP graph when graphs are enabled). Asynchronous. */
+/* Advances nsteps time steps. One step is the cascaded collision of f (Eq. 5-10) and
+ * of g with the heat source (Eq. 13-20, 23-25), then streaming (Eq. 11, 21) with the
+ * wall rules of Sec. 3 and Eq. (26)-(28), all fused per node as listed at the top of
+ * this file. One fused kernel per step, or one per two steps when steps_per_launch = 2;
+ * steps are replayed from a HIP graph when graphs are enabled. nsteps = 0 is a no-op,
+ * nsteps < 0 (or a NULL handle) returns CLBM_ERR_INVALID_ARG.
+ * Asynchronous; CLBM_ERR_HIP if a launch fails. */
 clbm_status clbm_step(clbm_handle* h, int nsteps);
 
-/* Writes rho, u_x, u_y, T at the current time; NULL outputs are skipped. Asynchronous. */
+/* Writes rho, u_x, u_y, T at the current time: rho and u as moments of f with half the
+ * force (Eq. 12), T as the moment of g with half the node's source (Eq. 25). Outputs are
+ * caller-owned device arrays of nx*ny floats, [ny][nx]; NULL outputs are skipped.
+ * Asynchronous. */
 clbm_status clbm_macros(clbm_handle* h, float* d_rho, float* d_ux, float* d_uy, float* d_T);
 
 /* Writes the stored post-collision state as float32 deviations: d_f [9][ny][nx]
@@ -181,8 +189,12 @@ clbm_status clbm_macros(clbm_handle* h, float* d_rho, float* d_ux, float* d_uy, 
  * NULL outputs are skipped. Asynchronous. */
 clbm_status clbm_populations(clbm_handle* h, float* d_f, float* d_g);
 
-/* Reduces the diagnostics over the lattice (wavefront and workgroup reductions,
- * then a fixed-order FP64 pass) and replaces the residual snapshot with the current
+/* Reduces the diagnostics over the lattice: the wall gradients and wall temperatures
+ * (Eq. 27-28) from which the average Nusselt number along a wall of the natural-convection
+ * cavity follows (Sec. 3.3, Table 1), mass, and the change since the last snapshot (the
+ * steady-state residual; the paper states no criterion, see clbm_diag). Wavefront and
+ * workgroup reductions, then a fixed-order FP64 pass; the partial sums live in the
+ * handle's workspace. Replaces the residual snapshot with the current
  * fields. Synchronises the stream. Returns CLBM_ERR_NAN (with *out filled) when a
  * non-finite value is found. */
 clbm_status clbm_diagnostics(clbm_handle* h, clbm_diag* out);
@@ -207,6 +219,15 @@ clbm_status clbm_load(clbm_handle* h, const void* d_src, long step);
 clbm_status clbm_get_step(const clbm_handle* h, long* step);
 clbm_status clbm_set_launch(clbm_handle* h, const clbm_launch* launch);
 clbm_status clbm_get_launch(const clbm_handle* h, clbm_launch* launch);
+/* A heat source given per node, added to the uniform Q (Sec. 3.2 treats a spatially
+ * variable source; Eq. (23)-(25) take the node's source): d_q is a device float32
+ * array [ny][nx] (row-major, x fastest) that the caller owns and keeps alive and
+ * unchanged while the handle steps; NULL removes it. The step then reads 4 more bytes
+ * per node. The state stored so far keeps its meaning: T is recovered from the stored
+ * populations as sum g* - Q/2 with the node's current source, so set the field before
+ * clbm_init_from_fields (or change it only where the source changes anyway). Rebuilds
+ * the handle's graphs. */
+clbm_status clbm_set_source_field(clbm_handle* h, const float* d_q);
 /* steps_per_graph = 0 launches every step on the stream; an even value > 0 replays
  * graphs of that many steps (the default is 0). Both graphs (one per starting buffer)
  * are instantiated by this call; clbm_set_launch drops them and the next clbm_step
@@ -269,7 +290,10 @@ clbm_status clbm_batch_step(clbm_batch* b, int nsteps);
 /* Marks every instance running with zero steps, restores the full tile list and takes
  * the residual snapshot of the current state (asynchronous). */
 clbm_status clbm_batch_reset(clbm_batch* b);
-/* Advances the running instances until each has converged (max(res_u, res_T) < tol, the
+/* Runs every instance to its steady state, the end point of the natural-convection and
+ * source tests of Sec. 3 (the paper gives no stopping rule; this one is the relative
+ * change of u and T over a window, as in clbm_diag). Advances the running instances with
+ * the step of clbm_step until each has converged (max(res_u, res_T) < tol, the
  * residuals of windows of K steps), diverged (non-finite value or |u| > 0.5) or taken
  * max_steps steps since clbm_batch_reset, or until this call has advanced budget_steps
  * steps (budget_steps <= 0: no budget); a later call resumes. Convergence checks,
@@ -303,6 +327,9 @@ clbm_status clbm_batch_autotune(clbm_batch* b, int steps, const char* cache_path
 clbm_status clbm_batch_tune_lookup(const clbm_batch* b, const char* cache_path, clbm_batch_launch* out,
                                    int* found);
 clbm_status clbm_batch_set_launch(clbm_batch* b, const clbm_batch_launch* launch);
+/* Source field of instance i (as clbm_set_source_field: a device float32 [ny][nx] array the
+ * caller keeps alive, NULL removes it). Synchronises. */
+clbm_status clbm_batch_set_source_field(clbm_batch* b, int i, const float* d_q);
 
 /* ------------------------------------------------------------------------ */
 /* Warm-start network: a four-level convolutional encoder-decoder with skip    */

@@ -115,6 +115,8 @@ def _declare(L):
         "clbm_set_launch": (st, [_VP, ctypes.POINTER(clbm_launch)]),
         "clbm_get_launch": (st, [_VP, ctypes.POINTER(clbm_launch)]),
         "clbm_set_graph": (st, [_VP, ctypes.c_int]),
+        "clbm_set_source_field": (st, [_VP, _VP]),
+        "clbm_batch_set_source_field": (st, [_VP, ctypes.c_int, _VP]),
         "clbm_stream_copy": (st, [_VP, _VP, ctypes.c_size_t, _VP]),
         "clbm_net_param_count": (st, [ctypes.POINTER(clbm_net_desc), ctypes.POINTER(ctypes.c_size_t)]),
         "clbm_net_workspace_bytes": (st, [ctypes.POINTER(clbm_net_desc), ctypes.POINTER(ctypes.c_size_t)]),
@@ -286,6 +288,15 @@ class Solver:
                              self.workspace.numel(), _stream_ptr(self.stream), ctypes.byref(h)),
                "clbm_create")
         self._h = h
+        self._qfield = None
+        if prob.get("Q_field") is not None:
+            self.set_source_field(prob["Q_field"])
+
+    def set_source_field(self, q):
+        """Heat source per node added to Q (array-like [ny][nx], or None to remove it)."""
+        t = None if q is None else self._f(q)
+        self._qfield = t  # the kernels read it on every step
+        _check(lib().clbm_set_source_field(self._h, _addr(t)), "clbm_set_source_field")
 
     def _f(self, a):
         import torch
@@ -414,6 +425,10 @@ class Batch:
                "clbm_batch_create")
         self._h = h
         self._keep = {}
+        self._qfields = {}
+        for i, p in enumerate(self.probs):
+            if p.get("Q_field") is not None:
+                self.set_source_field(i, p["Q_field"])
         self.tuned_from_cache = False
         if tune_cache and launch is None:
             cached = self.cached_launch(tune_cache)
@@ -443,6 +458,18 @@ class Batch:
             fs.append(t)
         _check(lib().clbm_batch_init(self._h, int(i), *[_addr(t) for t in fs]), "clbm_batch_init")
         self._keep[i] = fs
+
+    def set_source_field(self, i, q):
+        """Heat source per node of instance i added to its Q ([ny][nx], or None)."""
+        import torch
+        t = None
+        if q is not None:
+            nx, ny = int(self.probs[i]["nx"]), int(self.probs[i]["ny"])
+            t = torch.as_tensor(q, dtype=torch.float32, device=self.device)
+            t = t.expand(ny, nx).contiguous() if t.dim() < 2 else t.contiguous()
+            assert tuple(t.shape) == (ny, nx), t.shape
+        self._qfields[i] = t  # the kernels read it on every step
+        _check(lib().clbm_batch_set_source_field(self._h, int(i), _addr(t)), "clbm_batch_set_source_field")
 
     def step(self, n=1):
         _check(lib().clbm_batch_step(self._h, int(n)), "clbm_batch_step")

@@ -38,8 +38,7 @@ __global__ void __launch_bounds__(256) k_init(S* __restrict__ dst, const Lattice
     typename Wide<S>::type fa[9], tb[5];
     equilibrium(drho, vx, vy, th, c.T0, a, b);
     NodeMacro m;
-    if (c.viscous) collide<float, true, typename Wide<S>::type>(c, a, b, fa, tb, m);
-    else collide<float, false, typename Wide<S>::type>(c, a, b, fa, tb, m);
+    collide_any(c, a, b, fa, tb, m, x, y);
     store_node(dst, c, x, y, fa, tb);
 }
 
@@ -53,7 +52,7 @@ __global__ void __launch_bounds__(256) k_macros(const S* __restrict__ src, const
     if (x >= c.nx || y >= c.ny) return;
     float a[9], b[5];
     load_own(src, c, node_off(c, x, y), a, b);
-    const NodeMacro m = c.viscous ? macros_from_post<true>(c, a, b) : macros_from_post(c, a, b);
+    const NodeMacro m = macros_any(c, a, b, x, y);
     const size_t k = (size_t)y * c.nx + x;
     if (rho) rho[k] = 1.f + m.drho;
     if (ux) ux[k] = m.ux;
@@ -107,7 +106,7 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag(const S* __restrict__ src, 
         const size_t own = node_off(c, x, y);
         float a[9], b[5];
         load_own(src, c, own, a, b);
-        const NodeMacro m = c.viscous ? macros_from_post<true>(c, a, b) : macros_from_post(c, a, b);
+        const NodeMacro m = macros_any(c, a, b, x, y);
         const float T = c.T0 + m.theta;
         const bool bad = !(isfinite(m.drho) && isfinite(m.ux) && isfinite(m.uy) && isfinite(T));
         acc[0] += m.drho;
@@ -131,7 +130,7 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag(const S* __restrict__ src, 
             const int x2 = s == 0 ? x + 1 : (s == 1 ? x - 1 : x);
             const int y2 = s == 2 ? y + 1 : (s == 3 ? y - 1 : y);
             const size_t o2 = node_off(c, x2, y2);
-            const float th2 = c.viscous ? theta_post<S, true>(src, c, o2) : theta_post<S, false>(src, c, o2);
+            const float th2 = theta_post_any<S>(src, c, o2, x2, y2);
             const float thw = c.a1[s] * m.theta + c.a2[s] * th2 + c.a3[s];
             acc[5 + s] += (8.0 * thw - 9.0 * m.theta + th2) / 3.0;
             acc[9 + s] += (double)c.T0 + thw;

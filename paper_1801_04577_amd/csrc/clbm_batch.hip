@@ -54,13 +54,15 @@ __global__ void __launch_bounds__(1024) k_batch_step(const BatchInst* __restrict
             float a[9], b[5];
             W fa[9], tb[5];
             NodeMacro m;
-            if (c.viscous) {
-                gather_node<S, true, unsigned>(src, c, x, y, a, b);
-                collide<float, true, W>(c, a, b, fa, tb, m);
-            } else {
-                gather_node<S, false, unsigned>(src, c, x, y, a, b);
-                collide<float, false, W>(c, a, b, fa, tb, m);
+            switch (runtime_src(c)) {
+                case kSrcVisc: gather_node<S, kSrcVisc, unsigned>(src, c, x, y, a, b); break;
+                case kSrcField: gather_node<S, kSrcField, unsigned>(src, c, x, y, a, b); break;
+                case kSrcVisc | kSrcField:
+                    gather_node<S, kSrcVisc | kSrcField, unsigned>(src, c, x, y, a, b);
+                    break;
+                default: gather_node<S, 0, unsigned>(src, c, x, y, a, b); break;
             }
+            collide_any(c, a, b, fa, tb, m, x, y);
             store_node<S, unsigned>(dst, c, x, y, fa, tb);
         }
         }
@@ -86,11 +88,13 @@ __device__ __forceinline__ int banded_tile(int k, int n)
 // Two time steps of every instance on the active tile list (tiles of kBlock x TY nodes,
 // NT threads, grid-stride over tiles; the LDS tile is reused by each tile a workgroup
 // takes). Per tile it runs the phases of k_step2, so two steps here are two steps of
-// k_batch_step bit for bit. VH: 0 = no instance has viscous heating, 1 = all have, 2 =
-// mixed (both paths compiled in; the register budget is held at four waves per SIMD).
+// k_batch_step bit for bit. MODE: 0 = no instance has viscous heating or a source field,
+// 1 = all have viscous heating and none a field, 2 = anything else (every combination of
+// source terms compiled in, chosen per tile; the register budget is held at four waves
+// per SIMD).
 // bands != 0 deals the list to the XCDs in contiguous bands (banded_tile), else every
 // workgroup strides over the whole list.
-template <typename S, int VH, int TY, int NT>
+template <typename S, int MODE, int TY, int NT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_batch_step2(const BatchInst* __restrict__ insts,
                                                                     const int2* __restrict__ list,
                                                                     const int* __restrict__ count,
@@ -111,14 +115,23 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_
         const int X0 = (id % tiles_x) * (int)kBlock, Y0 = (id / tiles_x) * TY;
         const S* src = reinterpret_cast<const S*>(I.buf[parity]);
         S* dst = reinterpret_cast<S*>(I.buf[parity ^ 1]);
-        if (VH == 1 || (VH == 2 && c.viscous)) {
-            step2_phase1<S, true, TY, NT, unsigned>(src, c, tile, X0, Y0, tid);
+        const int src_terms = MODE == 0 ? 0 : MODE == 1 ? kSrcVisc : uniform_int(runtime_src(c));
+        if (src_terms == kSrcVisc) {
+            step2_phase1<S, kSrcVisc, TY, NT, unsigned>(src, c, tile, X0, Y0, tid);
             __syncthreads();
-            step2_phase2<S, true, TY, NT, unsigned>(dst, c, tile, X0, Y0, tid);
+            step2_phase2<S, kSrcVisc, TY, NT, unsigned>(dst, c, tile, X0, Y0, tid);
+        } else if (MODE == 2 && src_terms == kSrcField) {
+            step2_phase1<S, kSrcField, TY, NT, unsigned>(src, c, tile, X0, Y0, tid);
+            __syncthreads();
+            step2_phase2<S, kSrcField, TY, NT, unsigned>(dst, c, tile, X0, Y0, tid);
+        } else if (MODE == 2 && src_terms == (kSrcVisc | kSrcField)) {
+            step2_phase1<S, kSrcVisc | kSrcField, TY, NT, unsigned>(src, c, tile, X0, Y0, tid);
+            __syncthreads();
+            step2_phase2<S, kSrcVisc | kSrcField, TY, NT, unsigned>(dst, c, tile, X0, Y0, tid);
         } else {
-            step2_phase1<S, false, TY, NT, unsigned>(src, c, tile, X0, Y0, tid);
+            step2_phase1<S, 0, TY, NT, unsigned>(src, c, tile, X0, Y0, tid);
             __syncthreads();
-            step2_phase2<S, false, TY, NT, unsigned>(dst, c, tile, X0, Y0, tid);
+            step2_phase2<S, 0, TY, NT, unsigned>(dst, c, tile, X0, Y0, tid);
         }
         __syncthreads();  // the next tile overwrites the LDS tile
     }
@@ -169,7 +182,7 @@ __global__ void __launch_bounds__(1024) k_batch_diag(const BatchInst* __restrict
             float* snap = reinterpret_cast<float*>(I.snap);
             float a[9], b[5];
             load_own(src, c, node_off(c, x, y), a, b);
-            const NodeMacro m = c.viscous ? macros_from_post<true>(c, a, b) : macros_from_post(c, a, b);
+            const NodeMacro m = macros_any(c, a, b, x, y);
             const float T = c.T0 + m.theta;
             const size_t k = (size_t)y * c.nx + x, np = (size_t)c.nx * c.ny;
             const double u2 = (double)m.ux * m.ux + (double)m.uy * m.uy;
@@ -493,12 +506,12 @@ clbm_status add_node(hipGraph_t g, hipGraphNode_t* prev, const void* fn, dim3 gr
     return CLBM_OK;
 }
 
-template <typename S, int VH>
+template <typename S, int MODE>
 const void* step2_rows(int rows)
 {
-    if (rows == 6) return reinterpret_cast<const void*>(&k_batch_step2<S, VH, 6, 256>);
-    if (rows == 30) return reinterpret_cast<const void*>(&k_batch_step2<S, VH, 30, 1024>);
-    return reinterpret_cast<const void*>(&k_batch_step2<S, VH, kTwoStepRows, kTwoStepThreads>);
+    if (rows == 6) return reinterpret_cast<const void*>(&k_batch_step2<S, MODE, 6, 256>);
+    if (rows == 30) return reinterpret_cast<const void*>(&k_batch_step2<S, MODE, 30, 1024>);
+    return reinterpret_cast<const void*>(&k_batch_step2<S, MODE, kTwoStepRows, kTwoStepThreads>);
 }
 
 template <typename S>
@@ -507,13 +520,16 @@ const void* step2_for(int vh, int rows)
     return vh == 0 ? step2_rows<S, 0>(rows) : vh == 1 ? step2_rows<S, 1>(rows) : step2_rows<S, 2>(rows);
 }
 
-// The two-step kernel for the batch's storage type, tile height and mix of instances with
-// and without viscous heating.
+// The two-step kernel for the batch's storage type, tile height and mix of source terms
+// (viscous heating, source fields) over its instances.
 const void* step2_kernel(const clbm_batch* b)
 {
-    int vh = 0;
-    for (int i = 0; i < b->n; ++i) vh += b->p[i].viscous_heating ? 1 : 0;
-    const int mix = vh == 0 ? 0 : (vh == b->n ? 1 : 2);
+    int vh = 0, qf = 0;
+    for (int i = 0; i < b->n; ++i) {
+        vh += b->p[i].viscous_heating ? 1 : 0;
+        qf += b->inst[i].c.qfield ? 1 : 0;
+    }
+    const int mix = qf > 0 ? 2 : vh == 0 ? 0 : (vh == b->n ? 1 : 2);
     return b->precision == CLBM_FP16_SHIFTED ? step2_for<__half>(mix, b->launch.tile_y)
                                              : step2_for<float>(mix, b->launch.tile_y);
 }
@@ -888,6 +904,16 @@ clbm_status clbm_batch_residual(clbm_batch* b, int i, double out[2])
     if (!b || i < 0 || i >= b->n || !out) return CLBM_ERR_INVALID_ARG;
     CLBM_HIP(hipMemcpyAsync(out, b->d_res + 2 * i, 2 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
     CLBM_HIP(hipStreamSynchronize(b->stream));
+    return CLBM_OK;
+}
+
+clbm_status clbm_batch_set_source_field(clbm_batch* b, int i, const float* d_q)
+{
+    if (!b || i < 0 || i >= b->n) return CLBM_ERR_INVALID_ARG;
+    b->inst[i].c.qfield = d_q;
+    CLBM_HIP(hipMemcpyAsync(b->d_inst + i, &b->inst[i], sizeof(BatchInst), hipMemcpyHostToDevice, b->stream));
+    CLBM_HIP(hipStreamSynchronize(b->stream));  // the host copy may change after return
+    drop_batch_graph(b);                        // the kernel variant may change with the mix
     return CLBM_OK;
 }
 

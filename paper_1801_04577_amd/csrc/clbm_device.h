@@ -55,7 +55,20 @@ struct LatticeConst {
     // in scalar registers instead of being converted per node).
     double d_sp, d_sm, d_snu, d_s3, d_h3, d_s4, d_l1, d_l2;
     double d_src2, d_src2_q, d_Q, d_Fx, d_Fy, d_gb, d_T0, d_vh_pre;
+    const float* qfield;       // nullptr, or a heat source per node [ny][nx] added to Q
 };
+
+// Source terms of a kernel instantiation (SRC bits): kSrcVisc adds the local viscous
+// dissipation to Q (Sec. 3.2), kSrcField adds the caller's source field Q(x, y).
+constexpr int kSrcVisc = 1, kSrcField = 2;
+
+// The source field at node (x, y) when the instantiation has one, else 0.
+template <int SRC>
+__device__ __forceinline__ float node_q(const LatticeConst& c, int x, int y)
+{
+    if constexpr ((SRC & kSrcField) != 0) return c.qfield[(size_t)(unsigned)y * (unsigned)c.nx + (unsigned)x];
+    else return 0.f;
+}
 
 // A collision constant in the arithmetic type R: the FP64 copy for R = double.
 template <typename R> __device__ __forceinline__ R kv(float f, double d);
@@ -247,16 +260,18 @@ __device__ __forceinline__ R dissipation(R coef, R c11, R c2d, R rho)
 // force on k10, k01; the change is shifted back to raw moments with N(-u) (the inverse
 // of Eq. 6b) and to populations with the inverse of Eq. (6a), and added to the incoming
 // populations: f* = f + M^-1 N(-u) Delta.
-// VH: the heat source is Q plus the local viscous dissipation (needs g_beta = 0, so
-// that the force does not depend on the temperature the source produces).
-template <typename R, bool VH = false, typename P = R>
+// SRC & kSrcVisc: the heat source is Q plus the local viscous dissipation (needs
+// g_beta = 0, so that the force does not depend on the temperature the source produces).
+// SRC & kSrcField: qx, the caller's source at this node, is added to Q.
+template <typename R, int SRC = 0, typename P = R>
 __device__ __forceinline__ void collide(const LatticeConst& c, const float a_in[9], const float b[5],
-                                        P fa[9], P tb[5], NodeMacro& m)
+                                        P fa[9], P tb[5], NodeMacro& m, float qx = 0.f)
 {
     const R third = R(1) / R(3), ninth = R(1) / R(9);
     // Eq. (25): T = sum g + Q/2; sum g = T0 + sum b.
     const float sb = (b[0] + b[1]) + (b[2] + b[3]) + b[4];
-    const float theta = sb + 0.5f * c.Q;
+    const float Qloc = (SRC & kSrcField) ? c.Q + qx : c.Q;
+    const float theta = sb + 0.5f * Qloc;
     // Eq. (2): gravity along -y.
     const R Fx = kv<R>(c.Fx, c.d_Fx);
     const R Fy = kv<R>(c.Fy, c.d_Fy) + kv<R>(c.g_beta, c.d_gb) * (R)theta;
@@ -346,10 +361,14 @@ __device__ __forceinline__ void collide(const LatticeConst& c, const float a_in[
     fa[6] = P(a_in[6]) + P(0.25) * P(t1 + t2);
     fa[8] = P(a_in[8]) + P(0.25) * P(t1 - t2);
 
-    if constexpr (VH) {
-        const R Qn = kv<R>(c.Q, c.d_Q) + dissipation<R>(kv<R>(c.vh_pre, c.d_vh_pre), c11, n20 - n02, rho);
+    if constexpr ((SRC & kSrcVisc) != 0) {
+        const R Q0 = (SRC & kSrcField) ? R(Qloc) : kv<R>(c.Q, c.d_Q);
+        const R Qn = Q0 + dissipation<R>(kv<R>(c.vh_pre, c.d_vh_pre), c11, n20 - n02, rho);
         collide_thermal(c, b, ux, uy, Qn, kv<R>(c.src2_q, c.d_src2_q) * Qn, tb);
         m.theta = (float)((R)sb + R(0.5) * Qn);
+    } else if constexpr ((SRC & kSrcField) != 0) {
+        collide_thermal(c, b, ux, uy, R(Qloc), kv<R>(c.src2_q, c.d_src2_q) * R(Qloc), tb);
+        m.theta = theta;
     } else {
         collide_thermal(c, b, ux, uy, kv<R>(c.Q, c.d_Q), kv<R>(c.src2, c.d_src2), tb);
         m.theta = theta;
@@ -396,15 +415,16 @@ __device__ __forceinline__ void equilibrium(float drho, float ux, float uy, floa
 
 // Macroscopic values at time t from the stored post-collision deviations at t:
 // collision conserves rho, adds F to the momentum and Q to sum g, so
-// T = sum g* - Q/2 and u = (sum f* e - F/2)/rho. With VH the Q of the node is
+// T = sum g* - Q/2 and u = (sum f* e - F/2)/rho. With a source field, qx (the node's
+// value) is part of Q; with viscous heating the dissipation part of the node's Q is
 // recovered from the post-collision central moments at that u.
-template <bool VH = false>
+template <int SRC = 0>
 __device__ __forceinline__ NodeMacro macros_from_post(const LatticeConst& c, const float a[9],
-                                                      const float b[5])
+                                                      const float b[5], float qx = 0.f)
 {
     NodeMacro m;
     const float sb = (b[0] + b[1]) + (b[2] + b[3]) + b[4];
-    m.theta = sb - 0.5f * c.Q;
+    m.theta = sb - 0.5f * ((SRC & kSrcField) ? c.Q + qx : c.Q);
     const float Fx = c.Fx;
     const float Fy = c.Fy + c.g_beta * m.theta;
     const float p56 = a[5] + a[6], m56 = a[5] - a[6];
@@ -416,7 +436,7 @@ __device__ __forceinline__ NodeMacro macros_from_post(const LatticeConst& c, con
     m.drho = d;
     m.ux = (jx - 0.5f * Fx) * inv;
     m.uy = (jy - 0.5f * Fy) * inv;
-    if constexpr (VH) {
+    if constexpr ((SRC & kSrcVisc) != 0) {
         // Central k11 and k20 - k02 of the post-collision deviations (the rest weights
         // contribute to neither).
         const float rho = 1.f + d;
@@ -427,6 +447,45 @@ __device__ __forceinline__ NodeMacro macros_from_post(const LatticeConst& c, con
         m.theta -= 0.5f * dissipation<float>(c.vh_post, c11, c2d, rho);
     }
     return m;
+}
+
+}  // namespace clbm
+
+namespace clbm {
+
+// The source terms of a lattice as kernels see them at run time (the per-node kernels
+// outside the time step dispatch on it).
+__device__ __forceinline__ int runtime_src(const LatticeConst& c)
+{
+    return (c.viscous ? kSrcVisc : 0) | (c.qfield ? kSrcField : 0);
+}
+
+// macros_from_post with the source terms decided at run time, for node (x, y).
+__device__ __forceinline__ NodeMacro macros_any(const LatticeConst& c, const float a[9], const float b[5],
+                                                int x, int y)
+{
+    switch (runtime_src(c)) {
+        case kSrcVisc: return macros_from_post<kSrcVisc>(c, a, b);
+        case kSrcField: return macros_from_post<kSrcField>(c, a, b, node_q<kSrcField>(c, x, y));
+        case kSrcVisc | kSrcField:
+            return macros_from_post<kSrcVisc | kSrcField>(c, a, b, node_q<kSrcField>(c, x, y));
+        default: return macros_from_post<0>(c, a, b);
+    }
+}
+
+// collide with the source terms decided at run time, for node (x, y).
+template <typename P>
+__device__ __forceinline__ void collide_any(const LatticeConst& c, const float a[9], const float b[5], P fa[9],
+                                            P tb[5], NodeMacro& m, int x, int y)
+{
+    switch (runtime_src(c)) {
+        case kSrcVisc: collide<float, kSrcVisc, P>(c, a, b, fa, tb, m); break;
+        case kSrcField: collide<float, kSrcField, P>(c, a, b, fa, tb, m, node_q<kSrcField>(c, x, y)); break;
+        case kSrcVisc | kSrcField:
+            collide<float, kSrcVisc | kSrcField, P>(c, a, b, fa, tb, m, node_q<kSrcField>(c, x, y));
+            break;
+        default: collide<float, 0, P>(c, a, b, fa, tb, m); break;
+    }
 }
 
 }  // namespace clbm

@@ -67,34 +67,48 @@ __device__ __forceinline__ void load_own(const S* __restrict__ src, const Lattic
 }
 
 // T - T0 at time t of the node at element offset off, from its post-collision
-// populations: sum g* - Q/2, with Q the node's own source under VH.
-template <bool VH, typename S, unsigned P, typename Off>
-__device__ __forceinline__ float theta_at(const S* p, const LatticeConst& c, Off off)
+// populations: sum g* - Q/2, with Q the node's own source (qx its source-field value).
+template <int SRC, typename S, unsigned P, typename Off>
+__device__ __forceinline__ float theta_at(const S* p, const LatticeConst& c, Off off, float qx)
 {
     const S* gs = p + 9 * P;
-    if constexpr (VH) {
+    if constexpr ((SRC & kSrcVisc) != 0) {
         float a[9], b[5];
         load_pops<S, P>(p, off, a, b);
-        return macros_from_post<true>(c, a, b).theta;
+        return macros_from_post<SRC>(c, a, b, qx).theta;
     } else {
         const float s = ld(gs + off) + ld(gs + P + off) + ld(gs + 2 * P + off) + ld(gs + 3 * P + off)
                         + ld(gs + 4 * P + off);
-        return s - 0.5f * c.Q;
+        return s - 0.5f * ((SRC & kSrcField) ? c.Q + qx : c.Q);
     }
 }
 
-template <typename S, bool VH>
+template <typename S, int SRC>
 __device__ __forceinline__ float theta_post(const S* __restrict__ src, const LatticeConst& c,
-                                            size_t off)
+                                            size_t off, float qx)
 {
-    return theta_at<VH, S, kBlock>(src, c, off);
+    return theta_at<SRC, S, kBlock>(src, c, off, qx);
+}
+
+// theta_post with the source terms decided at run time, for node (x, y) at offset off.
+template <typename S>
+__device__ __forceinline__ float theta_post_any(const S* __restrict__ src, const LatticeConst& c,
+                                                size_t off, int x, int y)
+{
+    switch (runtime_src(c)) {
+        case kSrcVisc: return theta_post<S, kSrcVisc>(src, c, off, 0.f);
+        case kSrcField: return theta_post<S, kSrcField>(src, c, off, node_q<kSrcField>(c, x, y));
+        case kSrcVisc | kSrcField:
+            return theta_post<S, kSrcVisc | kSrcField>(src, c, off, node_q<kSrcField>(c, x, y));
+        default: return theta_post<S, 0>(src, c, off, 0.f);
+    }
 }
 
 // Gather the pre-collision deviations of node (x, y) at time t+1 from the
 // post-collision populations at time t, with all wall substitutions applied.
-// VH: the heat source includes the viscous dissipation (wall temperatures need the
-// source of the nodes they are extrapolated from).
-template <bool VH, typename Mem>
+// SRC: the source terms (wall temperatures need the source of the nodes they are
+// extrapolated from).
+template <int SRC, typename Mem>
 __device__ __forceinline__ void gather_mem(const Mem& mem, const LatticeConst& c, int x, int y,
                                            float a[9], float b[5])
 {
@@ -135,22 +149,24 @@ __device__ __forceinline__ void gather_mem(const Mem& mem, const LatticeConst& c
         // Eq. (26): g_i(x_f, t+1) = -g*_opp(i)(x_f, t) + c_T^2 T_w, with T_w from Eq. (28)
         // using T at this node (T1) and one node further from the wall (T2) at time t.
         // Post-collision data give T = sum g* - Q/2 (the collision adds Q).
-        auto theta = [&](Off off) { return theta_at<VH, typename Mem::Elem, P>(src, c, off); };
-        const float th1 = theta(own);
+        auto theta = [&](Off off, int qx, int qy) {
+            return theta_at<SRC, typename Mem::Elem, P>(src, c, off, node_q<SRC>(c, qx, qy));
+        };
+        const float th1 = theta(own, x, y);
         if (oxm) {
-            const float tw = c.a1[0] * th1 + c.a2[0] * theta(rC + mem.col(x, 1)) + c.a3[0];
+            const float tw = c.a1[0] * th1 + c.a2[0] * theta(rC + mem.col(x, 1), x + 1, y) + c.a3[0];
             b[1] = -b[1] + CT2 * tw;
         }
         if (oxp) {
-            const float tw = c.a1[1] * th1 + c.a2[1] * theta(rC + mem.col(x, -1)) + c.a3[1];
+            const float tw = c.a1[1] * th1 + c.a2[1] * theta(rC + mem.col(x, -1), x - 1, y) + c.a3[1];
             b[3] = -b[3] + CT2 * tw;
         }
         if (oym) {
-            const float tw = c.a1[2] * th1 + c.a2[2] * theta(mem.row(y, 1) + cC) + c.a3[2];
+            const float tw = c.a1[2] * th1 + c.a2[2] * theta(mem.row(y, 1) + cC, x, y + 1) + c.a3[2];
             b[2] = -b[2] + CT2 * tw;
         }
         if (oyp) {
-            const float tw = c.a1[3] * th1 + c.a2[3] * theta(mem.row(y, -1) + cC) + c.a3[3];
+            const float tw = c.a1[3] * th1 + c.a2[3] * theta(mem.row(y, -1) + cC, x, y - 1) + c.a3[3];
             b[4] = -b[4] + CT2 * tw;
         }
         if (c.moving) {
@@ -173,11 +189,11 @@ __device__ __forceinline__ void gather_mem(const Mem& mem, const LatticeConst& c
 }
 
 // Gather from the stored buffer.
-template <typename S, bool VH = false, typename O = size_t>
+template <typename S, int SRC = 0, typename O = size_t>
 __device__ __forceinline__ void gather_node(const S* __restrict__ src, const LatticeConst& c, int x,
                                             int y, float a[9], float b[5])
 {
-    gather_mem<VH>(global_mem<O>(src, c), c, x, y, a, b);
+    gather_mem<SRC>(global_mem<O>(src, c), c, x, y, a, b);
 }
 
 // Round the post-collision state of one node (x, y) into the storage type: the
@@ -301,7 +317,7 @@ __device__ __forceinline__ int tile_of_block(int total, int remap)
     return (b & 7) * per + (b >> 3);
 }
 
-template <typename S, int ROWS, bool VH, typename O>
+template <typename S, int ROWS, int SRC, typename O>
 __global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __restrict__ dst,
                                                const LatticeConst c, int tiles_x, int tiles_total,
                                                int remap)
@@ -327,7 +343,7 @@ __global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __r
             W fa[9], tb[5];
             NodeMacro m;
             gather_interior<S, kBlock>(rc - rb, rc, rc + rb, k, a, b);
-            collide<float, VH, W>(c, a, b, fa, tb, m);
+            collide<float, SRC, W>(c, a, b, fa, tb, m, node_q<SRC>(c, x, yw + r));
             store_node_at(reinterpret_cast<S*>(stored_row(dst, c.rowlen, yw + r) + k.c), fa, tb, x, yw + r);
         }
         return;
@@ -339,9 +355,9 @@ __global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __r
         if (y < c.ny) {
             float a[9], b[5];
             W fa[9], tb[5];
-            gather_node<S, VH, O>(src, c, x, y, a, b);
+            gather_node<S, SRC, O>(src, c, x, y, a, b);
             NodeMacro m;
-            collide<float, VH, W>(c, a, b, fa, tb, m);
+            collide<float, SRC, W>(c, a, b, fa, tb, m, node_q<SRC>(c, x, y));
             store_node<S, O>(dst, c, x, y, fa, tb);
         }
     }
@@ -393,7 +409,7 @@ __device__ __forceinline__ bool tile_interior(const LatticeConst& c, int X0, int
 // (X0 - 1 + lx, Y0 - 1 + ly) of the tile with its ring, advanced from the stored buffer
 // into LDS. In a periodic direction a ring node outside the lattice is the wrapped
 // node; in a walled one it does not exist and its LDS entry is never read.
-template <typename S, bool VH, int TY, int NT, typename O>
+template <typename S, int SRC, int TY, int NT, typename O>
 __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const LatticeConst& c, S* tile,
                                              int X0, int Y0, int tid)
 {
@@ -405,7 +421,7 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
     auto finish = [&](const float a[9], const float b[5], int gx, int gy, int lx, int ly) {
         W fa[9], tb[5];
         NodeMacro m;
-        collide<float, VH, W>(c, a, b, fa, tb, m);
+        collide<float, SRC, W>(c, a, b, fa, tb, m, node_q<SRC>(c, gx, gy));
         S v[14];
         round_node<S>(fa, tb, v, gx, gy);
         const unsigned o = (unsigned)ly * T::XE + lx;
@@ -423,7 +439,7 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
             gy = wrap_index(gy, c.ny);
         }
         float a[9], b[5];
-        gather_node<S, VH, O>(src, c, gx, gy, a, b);
+        gather_node<S, SRC, O>(src, c, gx, gy, a, b);
         finish(a, b, gx, gy, lx, ly);
     };
     // one wave per row for the kBlock interior columns, then the two ring columns
@@ -460,7 +476,7 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
 }
 
 // Phase 2 for thread tid: the tile's own nodes advanced from LDS and stored.
-template <typename S, bool VH, int TY, int NT, typename O>
+template <typename S, int SRC, int TY, int NT, typename O>
 __device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeConst& c, const S* tile,
                                              int X0, int Y0, int tid)
 {
@@ -485,7 +501,7 @@ __device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeC
             W fa[9], tb[5];
             NodeMacro m;
             gather_interior<S, T::P>(rc - rb, rc, rc + rb, k, a, b);
-            collide<float, VH, W>(c, a, b, fa, tb, m);
+            collide<float, SRC, W>(c, a, b, fa, tb, m, node_q<SRC>(c, gx, Y0 + ly));
             store_node_at(reinterpret_cast<S*>(stored_row(dst, c.rowlen, Y0 + ly) + own), fa, tb, gx, Y0 + ly);
         }
     } else if (gx < c.nx) {
@@ -497,14 +513,14 @@ __device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeC
             float a[9], b[5];
             W fa[9], tb[5];
             NodeMacro m;
-            gather_mem<VH>(mem, c, gx, gy, a, b);
-            collide<float, VH, W>(c, a, b, fa, tb, m);
+            gather_mem<SRC>(mem, c, gx, gy, a, b);
+            collide<float, SRC, W>(c, a, b, fa, tb, m, node_q<SRC>(c, gx, gy));
             store_node<S, O>(dst, c, gx, gy, fa, tb);
         }
     }
 }
 
-template <typename S, bool VH, int TY, int NT, typename O>
+template <typename S, int SRC, int TY, int NT, typename O>
 __global__ void __launch_bounds__(NT) k_step2(const S* __restrict__ src, S* __restrict__ dst,
                                               const LatticeConst c, int tiles_x, int tiles_total,
                                               int remap)
@@ -517,8 +533,8 @@ __global__ void __launch_bounds__(NT) k_step2(const S* __restrict__ src, S* __re
     if (t >= tiles_total) return;
     const int X0 = (t % tiles_x) * (int)kBlock;
     const int Y0 = (t / tiles_x) * TY;
-    step2_phase1<S, VH, TY, NT, O>(src, c, tile, X0, Y0, (int)threadIdx.x);
+    step2_phase1<S, SRC, TY, NT, O>(src, c, tile, X0, Y0, (int)threadIdx.x);
     __syncthreads();
-    step2_phase2<S, VH, TY, NT, O>(dst, c, tile, X0, Y0, (int)threadIdx.x);
+    step2_phase2<S, SRC, TY, NT, O>(dst, c, tile, X0, Y0, (int)threadIdx.x);
 }
 }  // namespace clbm

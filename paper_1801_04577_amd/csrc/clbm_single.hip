@@ -188,33 +188,49 @@ struct StepLaunch {
     int tiles_x, tiles_total, remap;
 };
 
-template <typename S, bool VH, typename O>
+template <typename S, int SRC, typename O>
 static const void* step_fn(int rows)
 {
     switch (rows) {
-        case 2: return reinterpret_cast<const void*>(&k_step<S, 2, VH, O>);
-        case 4: return reinterpret_cast<const void*>(&k_step<S, 4, VH, O>);
-        default: return reinterpret_cast<const void*>(&k_step<S, 1, VH, O>);
+        case 2: return reinterpret_cast<const void*>(&k_step<S, 2, SRC, O>);
+        case 4: return reinterpret_cast<const void*>(&k_step<S, 4, SRC, O>);
+        default: return reinterpret_cast<const void*>(&k_step<S, 1, SRC, O>);
     }
+}
+
+// Source terms of a lattice: viscous heating and/or a source field (kSrc* bits).
+static int lattice_src(const LatticeConst& c)
+{
+    return (c.viscous ? kSrcVisc : 0) | (c.qfield ? kSrcField : 0);
 }
 
 // Element offsets in the step kernels: 32-bit unless a population buffer holds 2^32
 // elements or more.
 static bool wide_offsets(const LatticeConst& c) { return (size_t)c.rowlen * c.ny >= 0xFFFFFFFFull; }
 
-template <typename S>
-static const void* step_fn(int rows, bool viscous, bool wide)
+template <typename S, typename O>
+static const void* step_fn_src(int rows, int src)
 {
-    if (wide) return viscous ? step_fn<S, true, size_t>(rows) : step_fn<S, false, size_t>(rows);
-    return viscous ? step_fn<S, true, unsigned>(rows) : step_fn<S, false, unsigned>(rows);
+    switch (src) {
+        case kSrcVisc: return step_fn<S, kSrcVisc, O>(rows);
+        case kSrcField: return step_fn<S, kSrcField, O>(rows);
+        case kSrcVisc | kSrcField: return step_fn<S, kSrcVisc | kSrcField, O>(rows);
+        default: return step_fn<S, 0, O>(rows);
+    }
+}
+
+template <typename S>
+static const void* step_fn(int rows, int src, bool wide)
+{
+    return wide ? step_fn_src<S, size_t>(rows, src) : step_fn_src<S, unsigned>(rows, src);
 }
 
 static StepLaunch plan_step(const LatticeConst& c, int precision, const clbm_launch& L)
 {
     StepLaunch s;
     const bool wide = wide_offsets(c);
-    s.fn = precision == CLBM_FP16_SHIFTED ? step_fn<__half>(L.rows_per_thread, c.viscous != 0, wide)
-                                          : step_fn<float>(L.rows_per_thread, c.viscous != 0, wide);
+    s.fn = precision == CLBM_FP16_SHIFTED ? step_fn<__half>(L.rows_per_thread, lattice_src(c), wide)
+                                          : step_fn<float>(L.rows_per_thread, lattice_src(c), wide);
     s.block = dim3(L.block_x, L.block_y, 1);
     s.tiles_x = (c.nx + L.block_x - 1) / L.block_x;
     const int rows_per_tile = L.block_y * L.rows_per_thread;
@@ -272,22 +288,30 @@ struct Step2Launch {
     int tiles_x, tiles_total, remap;
 };
 
-template <typename S, int TY, int NT>
-static const void* step2_fn(bool viscous, bool wide)
+template <typename S, int TY, int NT, typename O>
+static const void* step2_fn_o(int src)
 {
-    if (wide)
-        return viscous ? reinterpret_cast<const void*>(&k_step2<S, true, TY, NT, size_t>)
-                       : reinterpret_cast<const void*>(&k_step2<S, false, TY, NT, size_t>);
-    return viscous ? reinterpret_cast<const void*>(&k_step2<S, true, TY, NT, unsigned>)
-                   : reinterpret_cast<const void*>(&k_step2<S, false, TY, NT, unsigned>);
+    switch (src) {
+        case kSrcVisc: return reinterpret_cast<const void*>(&k_step2<S, kSrcVisc, TY, NT, O>);
+        case kSrcField: return reinterpret_cast<const void*>(&k_step2<S, kSrcField, TY, NT, O>);
+        case kSrcVisc | kSrcField:
+            return reinterpret_cast<const void*>(&k_step2<S, kSrcVisc | kSrcField, TY, NT, O>);
+        default: return reinterpret_cast<const void*>(&k_step2<S, 0, TY, NT, O>);
+    }
+}
+
+template <typename S, int TY, int NT>
+static const void* step2_fn(int src, bool wide)
+{
+    return wide ? step2_fn_o<S, TY, NT, size_t>(src) : step2_fn_o<S, TY, NT, unsigned>(src);
 }
 
 template <typename S>
-static const void* step2_for_rows(int rows, bool viscous, bool wide)
+static const void* step2_for_rows(int rows, int src, bool wide)
 {
-    if (rows == 6) return step2_fn<S, 6, 256>(viscous, wide);
-    if (rows == 30) return step2_fn<S, 30, 1024>(viscous, wide);
-    return step2_fn<S, kTwoStepRows, kTwoStepThreads>(viscous, wide);
+    if (rows == 6) return step2_fn<S, 6, 256>(src, wide);
+    if (rows == 30) return step2_fn<S, 30, 1024>(src, wide);
+    return step2_fn<S, kTwoStepRows, kTwoStepThreads>(src, wide);
 }
 
 static Step2Launch plan_step2(const LatticeConst& c, int precision, const clbm_launch& L)
@@ -295,8 +319,8 @@ static Step2Launch plan_step2(const LatticeConst& c, int precision, const clbm_l
     Step2Launch s;
     const bool f16 = precision == CLBM_FP16_SHIFTED;
     const int rows = L.two_step_rows ? L.two_step_rows : (f16 ? kTwoStepRowsF16 : kTwoStepRows);
-    s.fn = f16 ? step2_for_rows<__half>(rows, c.viscous != 0, wide_offsets(c))
-               : step2_for_rows<float>(rows, c.viscous != 0, wide_offsets(c));
+    s.fn = f16 ? step2_for_rows<__half>(rows, lattice_src(c), wide_offsets(c))
+               : step2_for_rows<float>(rows, lattice_src(c), wide_offsets(c));
     s.tiles_x = (c.nx + (int)kBlock - 1) / (int)kBlock;
     const int tiles_y = (c.ny + rows - 1) / rows;
     s.tiles_total = s.tiles_x * tiles_y;
@@ -814,6 +838,24 @@ clbm_status clbm_get_launch(const clbm_handle* h, clbm_launch* launch)
 {
     if (!h || !launch) return CLBM_ERR_INVALID_ARG;
     *launch = h->launch;
+    return CLBM_OK;
+}
+
+clbm_status clbm_set_source_field(clbm_handle* h, const float* d_q)
+{
+    if (!h) return CLBM_ERR_INVALID_ARG;
+    h->c.qfield = d_q;
+    // graphs hold the lattice constants by value: rebuild them with the field
+    const int g = h->graph_steps;
+    drop_graphs(h);
+    for (int start = 0; start < 2 && g > 0; ++start) {
+        const clbm_status st = build_graph(h, start);
+        if (st != CLBM_OK) {
+            drop_graphs(h);
+            h->graph_steps = 0;
+            return st;
+        }
+    }
     return CLBM_OK;
 }
 
