@@ -108,8 +108,8 @@ typedef struct {
  * maps consecutive tiles to the same XCD.
  * steps_per_launch = 2: two time steps per launch, the intermediate state kept in LDS
  * (rounded into the storage type exactly as a stored state) by workgroups that own tiles
- * of 64 x two_step_rows nodes: two_step_rows 6, 14 or 30 (256, 512 or 1024 threads; 0
- * selects 14);
+ * of 64 x two_step_rows nodes: two_step_rows 6, 14, 22 or 30 (256, 512, 512 or 1024
+ * threads; 0 selects 14 for FP32 storage and 22 for FP16 storage);
  * xcd_remap applies to these tiles too, the other fields shape only the single step that
  * ends an odd step count (256 x 1 threads, one row each, if they do not form a valid
  * shape). Both modes give bitwise identical states.
@@ -256,7 +256,7 @@ enum { CLBM_INST_RUNNING = 0, CLBM_INST_CONVERGED = 1, CLBM_INST_DIVERGED = 2,
 /* Tile shape of the batched kernel. steps_per_launch = 1: tile_x * tile_y nodes per
  * workgroup, one node per thread (tile_x a multiple of 64, tile_x * tile_y <= 1024).
  * steps_per_launch = 2: two time steps per launch with the intermediate state in LDS,
- * tiles of 64 x tile_y nodes with tile_y 6, 14 or 30 (256, 512 or 1024 threads; the LDS
+ * tiles of 64 x tile_y nodes with tile_y 6, 14, 22 or 30 (256, 512, 512 or 1024 threads; the LDS
  * tile of 66 x (tile_y + 2) nodes sets how many workgroups share a CU); bitwise equal to
  * one-step launches. persistent_wgs > 0 launches that many workgroups, each looping over
  * tiles; 0 launches one workgroup per tile. xcd_bands = 1 deals the tile list of a

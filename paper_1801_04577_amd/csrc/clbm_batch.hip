@@ -85,20 +85,28 @@ __device__ __forceinline__ int banded_tile(int k, int n)
     return j < band && t < n ? t : n;
 }
 
+// Waves per SIMD the LDS tile allows (160 KB per CU), at most four.
+template <typename S, int TY, int NT>
+constexpr int step2_waves_per_eu()
+{
+    constexpr int lds = 14 * Tile2<TY>::XE * Tile2<TY>::YE * (int)sizeof(S);
+    constexpr int w = (160 * 1024 / lds) * (NT / 64) / 4;
+    return w < 4 ? w : 4;
+}
+
 // Two time steps of every instance on the active tile list (tiles of kBlock x TY nodes,
 // NT threads, grid-stride over tiles; the LDS tile is reused by each tile a workgroup
 // takes). Per tile it runs the phases of k_step2, so two steps here are two steps of
 // k_batch_step bit for bit. MODE: 0 = no instance has viscous heating or a source field,
 // 1 = all have viscous heating and none a field, 2 = anything else (every combination of
-// source terms compiled in, chosen per tile; the register budget is held at four waves
-// per SIMD).
+// source terms compiled in, chosen per tile; the register budget is held at the waves
+// per SIMD the LDS tile allows, at most four).
 // bands != 0 deals the list to the XCDs in contiguous bands (banded_tile), else every
 // workgroup strides over the whole list.
 template <typename S, int MODE, int TY, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_batch_step2(const BatchInst* __restrict__ insts,
-                                                                    const int2* __restrict__ list,
-                                                                    const int* __restrict__ count,
-                                                                    int parity, int bands)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(step2_waves_per_eu<S, TY, NT>())))
+k_batch_step2(const BatchInst* __restrict__ insts, const int2* __restrict__ list, const int* __restrict__ count,
+              int parity, int bands)
 {
     __shared__ S tile[14 * Tile2<TY>::P];
     const int n = uniform_int(*count);
@@ -372,10 +380,6 @@ struct BatchLayout {
     int cap_tiles;
 };
 
-// Tile heights of the two-step kernel (kBlock columns): rows + 2 halo rows are dealt to
-// the waves of the workgroup, so the thread count is 64 (rows + 2) / 2.
-bool two_step_rows_ok(int rows) { return rows == 6 || rows == kTwoStepRows || rows == 30; }
-int two_step_threads(int rows) { return rows == 6 ? 256 : rows == 30 ? 1024 : kTwoStepThreads; }
 
 bool batch_launch_ok(const clbm_batch_launch& L)
 {
@@ -510,8 +514,9 @@ template <typename S, int MODE>
 const void* step2_rows(int rows)
 {
     if (rows == 6) return reinterpret_cast<const void*>(&k_batch_step2<S, MODE, 6, 256>);
+    if (rows == 22) return reinterpret_cast<const void*>(&k_batch_step2<S, MODE, 22, 512>);
     if (rows == 30) return reinterpret_cast<const void*>(&k_batch_step2<S, MODE, 30, 1024>);
-    return reinterpret_cast<const void*>(&k_batch_step2<S, MODE, kTwoStepRows, kTwoStepThreads>);
+    return reinterpret_cast<const void*>(&k_batch_step2<S, MODE, 14, 512>);
 }
 
 template <typename S>
@@ -932,7 +937,7 @@ clbm_status clbm_batch_autotune(clbm_batch* b, int steps, const char* cache_path
     static const int shapes[][3] = {{64, 1, 1}, {64, 2, 1}, {64, 4, 1}, {64, 8, 1}, {128, 1, 1},
                                     {128, 2, 1}, {128, 4, 1}, {256, 1, 1}, {256, 2, 1}, {256, 4, 1},
                                     {512, 1, 1}, {512, 2, 1}, {(int)kBlock, 6, 2},
-                                    {(int)kBlock, kTwoStepRows, 2}, {(int)kBlock, 30, 2}};
+                                    {(int)kBlock, 14, 2}, {(int)kBlock, 22, 2}, {(int)kBlock, 30, 2}};
     static const int wgs[] = {0, 2048, 8192};
     char sig[17];
     signature(b, sig);

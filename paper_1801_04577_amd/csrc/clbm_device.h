@@ -95,10 +95,60 @@ __device__ __forceinline__ size_t node_off(const LatticeConst& c, int x, int y)
     return (size_t)(unsigned)y * c.rowlen + ((unsigned)x / kBlock) * kBlockElems + ((unsigned)x % kBlock);
 }
 
+// The populations a node collides, as the fast paths load them: FP32 values, or for
+// binary16 storage the binary16 values themselves (In = _Float16). Their conversion to
+// FP32 is exact and is folded into the first sums the collision forms (in_add, in_sub)
+// and into the final addition of the change, so no separate conversion is issued.
+template <typename S> struct LoadT { typedef float type; };
+template <> struct LoadT<__half> { typedef _Float16 type; };
+
+template <typename R> __device__ __forceinline__ R in_val(float x) { return (R)x; }
+template <typename R> __device__ __forceinline__ R in_val(_Float16 x) { return (R)(float)x; }
+// x + y and x - y of two inputs in the arithmetic type R, rounded once (for binary16
+// inputs and R = float: one mixed-precision fma, x * 1 + y, on the binary16 operands).
+template <typename R> __device__ __forceinline__ R in_add(float x, float y) { return (R)x + (R)y; }
+template <typename R> __device__ __forceinline__ R in_sub(float x, float y) { return (R)x - (R)y; }
+template <typename R> __device__ __forceinline__ R in_add(_Float16 x, _Float16 y)
+{
+    return (R)(float)x + (R)(float)y;
+}
+template <typename R> __device__ __forceinline__ R in_sub(_Float16 x, _Float16 y)
+{
+    return (R)(float)x - (R)(float)y;
+}
+template <> __device__ __forceinline__ float in_add<float>(_Float16 x, _Float16 y)
+{
+    float r;
+    asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(x), "v"(y));
+    return r;
+}
+template <> __device__ __forceinline__ float in_sub<float>(_Float16 x, _Float16 y)
+{
+    float r;
+    asm("v_fma_mix_f32 %0, %2, -1.0, %1 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(x), "v"(y));
+    return r;
+}
+// x + y for an input x and a value y already in R.
+template <typename R> __device__ __forceinline__ R in_plus(float x, R y) { return (R)x + y; }
+template <typename R> __device__ __forceinline__ R in_plus(_Float16 x, R y) { return (R)(float)x + y; }
+template <> __device__ __forceinline__ float in_plus<float>(_Float16 x, float y)
+{
+    float r;
+    asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(x), "v"(y));
+    return r;
+}
+
 // Storage loads: float32 or binary16.
 template <typename S> __device__ __forceinline__ float ld(const S* p);
 template <> __device__ __forceinline__ float ld<float>(const float* p) { return *p; }
 template <> __device__ __forceinline__ float ld<__half>(const __half* p) { return __half2float(*p); }
+// Loads of the fast paths, as LoadT.
+template <typename S> __device__ __forceinline__ typename LoadT<S>::type ld_in(const S* p);
+template <> __device__ __forceinline__ float ld_in<float>(const float* p) { return *p; }
+template <> __device__ __forceinline__ _Float16 ld_in<__half>(const __half* p)
+{
+    return __builtin_bit_cast(_Float16, *p);
+}
 
 // Unbiased rounding into storage. x lies between the nearest storable value f and its
 // neighbour g on the other side of x; g is taken with probability |x - f|/|g - f|. The
@@ -191,16 +241,15 @@ struct NodeMacro {
 // Delta k20 = -lambda_2 (k20 - c_T^2 T) + (1 - lambda_2/2) c_T^2 Q (k02 alike); the
 // change is shifted back to raw moments (inverse of Eq. 17) and to populations
 // (inverse of Eq. 16) and added to the incoming populations, tb = b + Delta g.
-template <typename R, typename P>
-__device__ __forceinline__ void collide_thermal(const LatticeConst& c, const float b[5], R ux,
-                                                R uy, R Q, R src2, P tb[5])
+template <typename R, typename P, typename In>
+__device__ __forceinline__ void collide_thermal(const LatticeConst& c, const In b[5], R t10, R t01,
+                                                R t20, R t02, R sb, R ux, R uy, R Q, R src2, P tb[5])
 {
     const R T0 = kv<R>(c.T0, c.d_T0);
-    const R b0 = b[0], b1 = b[1], b2 = b[2], b3 = b[3], b4 = b[4];
-    // Raw moments of b (Eq. 16); the rest weights carry [T0, 0, 0, T0 c_T^2, T0 c_T^2].
-    const R sb = (b0 + b1) + (b2 + b3) + b4;
+    // Raw moments of b (Eq. 16), formed by the caller: sb = sum b, t10 = b1 - b3,
+    // t01 = b2 - b4, t20 = b1 + b3, t02 = b2 + b4; the rest weights carry
+    // [T0, 0, 0, T0 c_T^2, T0 c_T^2].
     const R theta = sb + R(0.5) * Q;               // Eq. (25), minus T0
-    const R t10 = b1 - b3, t01 = b2 - b4, t20 = b1 + b3, t02 = b2 + b4;
     const R K00 = T0 + sb;                          // full raw k00 = T - Q/2
     // Central moments (Eq. 17) minus their equilibria (Eq. 19).
     const R e10 = t10 - ux * K00;
@@ -220,11 +269,11 @@ __device__ __forceinline__ void collide_thermal(const LatticeConst& c, const flo
     const R r02 = d02 + uy * (R(2.0) * d01 + uy * Q);
     // Inverse of Eq. (16): the change of each population, added to the incoming one in P
     // (the factor 1/2 is exact and applied in P with the sum).
-    tb[0] = P(b[0]) + P(Q - r20 - r02);
-    tb[1] = P(b[1]) + P(0.5) * P(r20 + r10);
-    tb[3] = P(b[3]) + P(0.5) * P(r20 - r10);
-    tb[2] = P(b[2]) + P(0.5) * P(r02 + r01);
-    tb[4] = P(b[4]) + P(0.5) * P(r02 - r01);
+    tb[0] = in_val<P>(b[0]) + P(Q - r20 - r02);
+    tb[1] = in_val<P>(b[1]) + P(0.5) * P(r20 + r10);
+    tb[3] = in_val<P>(b[3]) + P(0.5) * P(r20 - r10);
+    tb[2] = in_val<P>(b[2]) + P(0.5) * P(r02 + r01);
+    tb[4] = in_val<P>(b[4]) + P(0.5) * P(r02 - r01);
 }
 
 // Viscous dissipation nu [(d_x u_y + d_y u_x)^2 + (d_x u_x - d_y u_y)^2] (Sec. 3.2 uses
@@ -243,7 +292,7 @@ __device__ __forceinline__ R dissipation(R coef, R c11, R c2d, R rho)
 }
 
 // Cascaded collision of one node. On entry a[9], b[5] hold the pre-collision
-// deviations at time t; on exit fa[9] and tb[5] hold the post-collision flow and
+// deviations at time t (In: FP32, or binary16 as loaded, see LoadT); on exit fa[9] and tb[5] hold the post-collision flow and
 // temperature deviations in the type P, to be rounded into storage by store_node.
 // m receives rho - 1, u and T - T0 at time t.
 // The arithmetic type R gives the change of each population; the change is added to the
@@ -263,30 +312,30 @@ __device__ __forceinline__ R dissipation(R coef, R c11, R c2d, R rho)
 // SRC & kSrcVisc: the heat source is Q plus the local viscous dissipation (needs
 // g_beta = 0, so that the force does not depend on the temperature the source produces).
 // SRC & kSrcField: qx, the caller's source at this node, is added to Q.
-template <typename R, int SRC = 0, typename P = R>
-__device__ __forceinline__ void collide(const LatticeConst& c, const float a_in[9], const float b[5],
+template <typename R, int SRC = 0, typename P = R, typename In = float>
+__device__ __forceinline__ void collide(const LatticeConst& c, const In a[9], const In b[5],
                                         P fa[9], P tb[5], NodeMacro& m, float qx = 0.f)
 {
     const R third = R(1) / R(3), ninth = R(1) / R(9);
+    // Raw moments of the temperature deviations (Eq. 16).
+    const R t20 = in_add<R>(b[1], b[3]), t10 = in_sub<R>(b[1], b[3]);
+    const R t02 = in_add<R>(b[2], b[4]), t01 = in_sub<R>(b[2], b[4]);
     // Eq. (25): T = sum g + Q/2; sum g = T0 + sum b.
-    const float sb = (b[0] + b[1]) + (b[2] + b[3]) + b[4];
+    const R sb = in_plus<R>(b[0], t20) + t02;
     const float Qloc = (SRC & kSrcField) ? c.Q + qx : c.Q;
-    const float theta = sb + 0.5f * Qloc;
+    const float theta = (float)sb + 0.5f * Qloc;
     // Eq. (2): gravity along -y.
     const R Fx = kv<R>(c.Fx, c.d_Fx);
     const R Fy = kv<R>(c.Fy, c.d_Fy) + kv<R>(c.g_beta, c.d_gb) * (R)theta;
-    R a[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) a[i] = a_in[i];
 
     // Raw moments of the deviations (Eq. 6a applied to a); the rest weights carry
     // [1, 0, 0, 1/3, 1/3, 0, 0, 0, 1/9].
-    const R s13 = a[1] + a[3], d13 = a[1] - a[3];
-    const R s24 = a[2] + a[4], d24 = a[2] - a[4];
-    const R p56 = a[5] + a[6], m56 = a[5] - a[6];
-    const R p78 = a[7] + a[8], m78 = a[7] - a[8];
+    const R s13 = in_add<R>(a[1], a[3]), d13 = in_sub<R>(a[1], a[3]);
+    const R s24 = in_add<R>(a[2], a[4]), d24 = in_sub<R>(a[2], a[4]);
+    const R p56 = in_add<R>(a[5], a[6]), m56 = in_sub<R>(a[5], a[6]);
+    const R p78 = in_add<R>(a[7], a[8]), m78 = in_sub<R>(a[7], a[8]);
     const R k22 = p56 + p78;                    // a5 + a6 + a7 + a8
-    const R d = a[0] + s13 + s24 + k22;         // rho - 1
+    const R d = in_plus<R>(a[0], s13) + s24 + k22;  // rho - 1
     const R jx = d13 + m56 - m78;               // k10
     const R jy = d24 + p56 - p78;               // k01
     const R k20 = s13 + k22;
@@ -351,26 +400,27 @@ __device__ __forceinline__ void collide(const LatticeConst& c, const float a_in[
     const R s1 = R11 + R22, s2 = R21 + R12;
     const R t1 = R22 - R11, t2 = R21 - R12;
     // (the factors 1/2 and 1/4 are exact, so they are applied in P together with the sum)
-    fa[0] = P(a_in[0]) - P(v1 + R02);
-    fa[1] = P(a_in[1]) + P(0.5) * P(v1 + u1);
-    fa[3] = P(a_in[3]) + P(0.5) * P(v1 - u1);
-    fa[2] = P(a_in[2]) + P(0.5) * P(v2 + u2);
-    fa[4] = P(a_in[4]) + P(0.5) * P(v2 - u2);
-    fa[5] = P(a_in[5]) + P(0.25) * P(s1 + s2);
-    fa[7] = P(a_in[7]) + P(0.25) * P(s1 - s2);
-    fa[6] = P(a_in[6]) + P(0.25) * P(t1 + t2);
-    fa[8] = P(a_in[8]) + P(0.25) * P(t1 - t2);
+    fa[0] = in_val<P>(a[0]) - P(v1 + R02);
+    fa[1] = in_val<P>(a[1]) + P(0.5) * P(v1 + u1);
+    fa[3] = in_val<P>(a[3]) + P(0.5) * P(v1 - u1);
+    fa[2] = in_val<P>(a[2]) + P(0.5) * P(v2 + u2);
+    fa[4] = in_val<P>(a[4]) + P(0.5) * P(v2 - u2);
+    fa[5] = in_val<P>(a[5]) + P(0.25) * P(s1 + s2);
+    fa[7] = in_val<P>(a[7]) + P(0.25) * P(s1 - s2);
+    fa[6] = in_val<P>(a[6]) + P(0.25) * P(t1 + t2);
+    fa[8] = in_val<P>(a[8]) + P(0.25) * P(t1 - t2);
 
     if constexpr ((SRC & kSrcVisc) != 0) {
         const R Q0 = (SRC & kSrcField) ? R(Qloc) : kv<R>(c.Q, c.d_Q);
         const R Qn = Q0 + dissipation<R>(kv<R>(c.vh_pre, c.d_vh_pre), c11, n20 - n02, rho);
-        collide_thermal(c, b, ux, uy, Qn, kv<R>(c.src2_q, c.d_src2_q) * Qn, tb);
-        m.theta = (float)((R)sb + R(0.5) * Qn);
+        collide_thermal(c, b, t10, t01, t20, t02, sb, ux, uy, Qn, kv<R>(c.src2_q, c.d_src2_q) * Qn, tb);
+        m.theta = (float)(sb + R(0.5) * Qn);
     } else if constexpr ((SRC & kSrcField) != 0) {
-        collide_thermal(c, b, ux, uy, R(Qloc), kv<R>(c.src2_q, c.d_src2_q) * R(Qloc), tb);
+        collide_thermal(c, b, t10, t01, t20, t02, sb, ux, uy, R(Qloc), kv<R>(c.src2_q, c.d_src2_q) * R(Qloc),
+                        tb);
         m.theta = theta;
     } else {
-        collide_thermal(c, b, ux, uy, kv<R>(c.Q, c.d_Q), kv<R>(c.src2, c.d_src2), tb);
+        collide_thermal(c, b, t10, t01, t20, t02, sb, ux, uy, kv<R>(c.Q, c.d_Q), kv<R>(c.src2, c.d_src2), tb);
         m.theta = theta;
     }
     m.drho = (float)d;

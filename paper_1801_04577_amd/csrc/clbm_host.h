@@ -27,10 +27,16 @@ constexpr size_t kAlign = 256;   // workspace region alignment, bytes
 
 // Two steps per launch: tiles of kBlock x kTwoStepRows nodes, kTwoStepThreads threads.
 constexpr int kTwoStepRows = 14;
-// FP16 storage: same tile (half the LDS, so three workgroups fit a CU).
-constexpr int kTwoStepRowsF16 = 14;
-constexpr int kTwoStepThreadsF16 = 512;
 constexpr int kTwoStepThreads = 512;
+// FP16 storage: taller tiles of 22 rows, three rows (with the halo) per wave of a
+// 512-thread workgroup: half the LDS per node, and 4.6% fewer ring nodes recomputed.
+constexpr int kTwoStepRowsF16 = 22;
+
+// Tile heights of the two-step kernel (kBlock columns) and their workgroup sizes: the
+// rows + 2 halo rows are dealt to the waves, two rows per wave (6, 14, 30 rows: 256, 512,
+// 1024 threads) or three (22 rows: 512 threads).
+inline bool two_step_rows_ok(int rows) { return rows == 6 || rows == 14 || rows == 22 || rows == 30; }
+inline int two_step_threads(int rows) { return rows == 6 ? 256 : rows == 30 ? 1024 : 512; }
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 

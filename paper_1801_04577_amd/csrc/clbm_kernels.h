@@ -283,12 +283,14 @@ __device__ __forceinline__ char* stored_row(S* p, unsigned rowlen, int y)
 
 // Pull gather (Eq. 11, Eq. 21) of an interior node from the rows y-1 (rm), y (rc), y+1 (rp)
 // of the post-collision populations at time t; P is the population stride in elements.
+// The values are loaded as LoadT<S> (binary16 storage keeps them in binary16).
 template <typename S, unsigned P>
 __device__ __forceinline__ void gather_interior(const char* rm, const char* rc, const char* rp,
-                                                const ColBytes k, float a[9], float b[5])
+                                                const ColBytes k, typename LoadT<S>::type a[9],
+                                                typename LoadT<S>::type b[5])
 {
     auto at = [&](const char* row, unsigned col, int i) {
-        return ld(reinterpret_cast<const S*>(row + col) + i * P);
+        return ld_in(reinterpret_cast<const S*>(row + col) + i * P);
     };
     a[0] = at(rc, k.c, 0);
     a[1] = at(rc, k.m, 1);
@@ -339,7 +341,7 @@ __global__ void __launch_bounds__(1024) k_step(const S* __restrict__ src, S* __r
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const char* rc = stored_row(src, c.rowlen, yw + r);
-            float a[9], b[5];
+            typename LoadT<S>::type a[9], b[5];
             W fa[9], tb[5];
             NodeMacro m;
             gather_interior<S, kBlock>(rc - rb, rc, rc + rb, k, a, b);
@@ -418,7 +420,7 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
     const int lane = tid % 64;
     const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
     constexpr int nwaves = NT / 64;
-    auto finish = [&](const float a[9], const float b[5], int gx, int gy, int lx, int ly) {
+    auto finish = [&](const auto* a, const auto* b, int gx, int gy, int lx, int ly) {
         W fa[9], tb[5];
         NodeMacro m;
         collide<float, SRC, W>(c, a, b, fa, tb, m, node_q<SRC>(c, gx, gy));
@@ -450,7 +452,7 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
         constexpr int R = T::YE / nwaves;
         const ColBytes k = stored_cols<S>(X0 + lane);
         const size_t rb = (size_t)c.rowlen * sizeof(S);
-        float a[R][9], b[R][5];
+        typename LoadT<S>::type a[R][9], b[R][5];
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const char* rc = stored_row(src, c.rowlen, Y0 - 1 + wave + j * nwaves);
@@ -464,7 +466,7 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
             const int lx = q < T::YE ? 0 : T::XE - 1, ly = q % T::YE;
             const int gx = X0 - 1 + lx, gy = Y0 - 1 + ly;
             const char* rc = stored_row(src, c.rowlen, gy);
-            float ra[9], rb9[5];
+            typename LoadT<S>::type ra[9], rb9[5];
             gather_interior<S, kBlock>(rc - rb, rc, rc + rb, stored_cols<S>(gx), ra, rb9);
             finish(ra, rb9, gx, gy, lx, ly);
         }
@@ -497,7 +499,7 @@ __device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeC
             const int ly = wave + j * nwaves;
             if (ly >= TY) break;
             const char* rc = reinterpret_cast<const char*>(tile) + (unsigned)(ly + 1) * rb;
-            float a[9], b[5];
+            typename LoadT<S>::type a[9], b[5];
             W fa[9], tb[5];
             NodeMacro m;
             gather_interior<S, T::P>(rc - rb, rc, rc + rb, k, a, b);

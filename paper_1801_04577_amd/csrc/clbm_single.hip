@@ -244,8 +244,6 @@ static StepLaunch plan_step(const LatticeConst& c, int precision, const clbm_lau
 
 // Tile heights of the two-step kernel and their thread counts (rows + 2 halo rows dealt to
 // the waves: 64 (rows + 2) / 2 threads).
-static bool two_step_rows_ok(int rows) { return rows == 6 || rows == kTwoStepRows || rows == 30; }
-static int two_step_threads(int rows) { return rows == 6 ? 256 : rows == 30 ? 1024 : kTwoStepThreads; }
 
 static bool launch_ok(const clbm_launch& L, int precision)
 {
@@ -310,8 +308,9 @@ template <typename S>
 static const void* step2_for_rows(int rows, int src, bool wide)
 {
     if (rows == 6) return step2_fn<S, 6, 256>(src, wide);
+    if (rows == 22) return step2_fn<S, 22, 512>(src, wide);
     if (rows == 30) return step2_fn<S, 30, 1024>(src, wide);
-    return step2_fn<S, kTwoStepRows, kTwoStepThreads>(src, wide);
+    return step2_fn<S, 14, 512>(src, wide);
 }
 
 static Step2Launch plan_step2(const LatticeConst& c, int precision, const clbm_launch& L)

@@ -134,7 +134,8 @@ def compare(net, probs, cold, grid, max_steps, tol, K, refine_tol=None):
     """Cold start (initial fields `cold`, one dict per problem) and network warm start of
     the same problems to the same residual: per-instance steps, status and Nusselt
     numbers of both. With refine_tol both runs are then continued to that residual and
-    their Nusselt numbers reported again (they must reach the same steady state)."""
+    their Nusselt numbers reported again (they must reach the same steady state), with
+    the steps each continuation took."""
     t0 = time.perf_counter()
     bc, steps_c, st_c = solve(probs, cold, max_steps, tol, K)
     nu_c = nusselt_numbers(bc, probs)
@@ -152,4 +153,5 @@ def compare(net, probs, cold, grid, max_steps, tol, K, refine_tol=None):
             steps, status = b.run(max_steps=max_steps, tol=refine_tol, K=K)
             out[key + "_refined_nu"] = nusselt_numbers(b, probs)
             out[key + "_refined_status"] = status
+            out[key + "_refined_steps"] = steps
     return out

@@ -51,7 +51,8 @@ def run_single(prob, fields, steps, precision=0):
                                     dict(tile_x=64, tile_y=14, persistent_wgs=40, steps_per_launch=2,
                                          xcd_bands=0),
                                     dict(tile_x=64, tile_y=6, persistent_wgs=0, steps_per_launch=2),
-                                    dict(tile_x=64, tile_y=30, persistent_wgs=24, steps_per_launch=2)])
+                                    dict(tile_x=64, tile_y=30, persistent_wgs=24, steps_per_launch=2),
+                                    dict(tile_x=64, tile_y=22, persistent_wgs=0, steps_per_launch=2)])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_batch_equals_single_lattices(launch, precision):
     """Every launch shape and both storage types: each instance bitwise equal to its
@@ -183,10 +184,10 @@ def test_autotune_writes_cache_and_keeps_results(tmp_path):
     assert b.cached_launch(cache) is None
     best = b.autotune(steps=4, cache_path=cache)
     lines = [json.loads(l) for l in open(cache)]
-    # at least 12 one-step shapes and 3 two-step heights x 2 dealing orders, one workgroup
+    # at least 12 one-step shapes and 4 two-step heights x 2 dealing orders, one workgroup
     # per tile (persistent counts at or above the tile count are skipped), and the best line
-    assert len(lines) >= 12 + 6 + 1 and all(l["ms_per_step"] > 0 for l in lines)
-    assert {l["tile_y"] for l in lines if l.get("steps_per_launch") == 2} == {6, 14, 30}
+    assert len(lines) >= 12 + 8 + 1 and all(l["ms_per_step"] > 0 for l in lines)
+    assert {l["tile_y"] for l in lines if l.get("steps_per_launch") == 2} == {6, 14, 22, 30}
     assert {l["xcd_bands"] for l in lines if l.get("steps_per_launch") == 2} == {0, 1}
     assert lines[-1]["best"] == 1 and len({l["signature"] for l in lines}) == 1
     assert best["tile_x"] % 64 == 0

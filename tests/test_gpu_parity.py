@@ -317,11 +317,12 @@ def test_interior_blocks_fp16(kind):
             assert torch.equal(x, y)
 
 
-@pytest.mark.parametrize("rows", [6, 30])
+@pytest.mark.parametrize("rows", [6, 14, 22, 30])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("case", ["seed3", "walls", "periodic", "viscous"])
 def test_two_step_tile_heights(rows, precision, case):
-    """Two-step tiles of 64 x 6 and 64 x 30 nodes (256 and 1024 threads) give the state of
+    """Two-step tiles of 64 x 6, 14, 22 and 30 nodes (256, 512, 512 and 1024 threads; three
+    rows per wave at 22) give the state of
     one-step launches bit for bit, for both storage types, at walls, in interior tiles, in
     a fully periodic lattice and with viscous heating; 37 steps end with a one-step launch."""
     import torch

@@ -69,7 +69,7 @@ def test_field_launch_shapes_bitwise(kind):
     runs = [run_gpu(prob, 37, fields, launch=dict(block_x=256, steps_per_launch=1))]
     runs.append(run_gpu(prob, 37, fields, launch=dict(block_x=64, block_y=4, rows_per_thread=2,
                                                       xcd_remap=1, steps_per_launch=1)))
-    for rows in (6, 14, 30):
+    for rows in (6, 14, 22, 30):
         runs.append(run_gpu(prob, 37, fields, launch=dict(steps_per_launch=2, xcd_remap=1, two_step_rows=rows)))
     for r in runs[1:]:
         for x, y in zip(runs[0].populations(), r.populations()):
