@@ -62,3 +62,54 @@ def test_valu_summary(tmp_path):
     assert prof["valu_frac_of_peak"] == pytest.approx(300.0 / 614.4, abs=1e-4)
     assert prof["valu_instructions_per_node_launch"] == pytest.approx(1.5e8 * 64 / 4096)
     assert os.path.exists(tmp_path / "step_cavity64_fp32_valu.md")
+
+
+def test_more_than_one_gpu_is_refused():
+    """bench.py measures one GPU: --gpus 2 exits with status 2 and says why, before any
+    GPU work."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_launch_and_graph_counts():
+    """Launches of a timed region and graph lengths: two-step launches end an odd count with
+    one one-step launch; graphs hold an even number of steps between diagnostics."""
+    assert bench.launches_of(2000, 2) == 1000 and bench.launches_of(21, 2) == 11
+    assert bench.launches_of(21, 1) == 21
+    assert bench.graph_steps(2000, 100) == 100 and bench.graph_steps(20, 100) == 20
+    assert bench.graph_steps(15, 0) == 14 and bench.graph_steps(1, 100) == 0
+    assert bench.arithmetic_dtype("fp16s") == "f32" and bench.arithmetic_dtype("fp32") == "f32"
+
+
+def test_warmstart_summary_renders(tmp_path):
+    """The warm-start summary writer on a small result of the shape the experiment returns."""
+    inst = [{"Ra": 1e5, "Pr": 0.71, "Qstar": 1.0, "cold_steps": 1000, "warm_steps": 400,
+             "cold_nu": 4.5, "warm_nu": 4.52, "cold_refined_nu": 4.51, "warm_refined_nu": 4.511,
+             "cold_steps_to_nu": 2000, "warm_steps_to_nu": 500}]
+    res = {"grid": 128, "train_states": 10, "train_requested": 10, "generate_seconds": 1.0,
+           "generate_mlups": 100.0, "train_steps": 5, "train_batch": 2, "train_seconds": 0.5,
+           "train_tflops": 1.0, "loss_first": 1.0, "loss_last": 0.1,
+           "eval": {"cavities": 1, "side": 64, "both_converged": 1, "cold_steps_total": 1000,
+                    "warm_steps_total": 400, "steps_ratio_warm_over_cold": 0.4, "median_ratio": 0.4,
+                    "cold_seconds": 1.0, "warm_seconds": 0.5, "nu_rel_diff_max": 4e-3,
+                    "nu_rel_diff_mean": 4e-3, "per_instance": inst,
+                    "refine": {"tol": 1e-9, "nu_rel_diff_max": 2e-4, "nu_within_1e-3": 1,
+                               "both_converged": 1, "warm_at_1e-7_vs_steady_max": 2e-3,
+                               "cold_at_1e-7_vs_steady_max": 2e-3,
+                               "warm_at_1e-7_within_1e-3_of_steady": 0,
+                               "cold_at_1e-7_within_1e-3_of_steady": 0,
+                               "cold_steps_to_tol_total": 3000, "warm_steps_to_tol_total": 1500,
+                               "steps_ratio_to_tol": 0.5, "cold_steps_to_nu_1e-3_total": 2000,
+                               "warm_steps_to_nu_1e-3_total": 500, "steps_ratio_to_nu_1e-3": 0.25,
+                               "median_ratio_to_nu_1e-3": 0.25, "nu_settled_both": 1,
+                               "nu_settle_chunk_steps": 100, "cold_seconds": 1.0, "warm_seconds": 0.5}}}
+    out = tmp_path / "ws.md"
+    bench.write_ws_summary(res, str(out), "python bench.py --warmstart")
+    text = out.read_text()
+    assert "0.25; 0.25" in text and "| 1.00e+05 | 0.71 | 1.00 | 1000 | 400 | 0.40 |" in text
+    assert "cd /root/repo && python bench.py --warmstart" in text
