@@ -477,6 +477,50 @@ __device__ __forceinline__ void step2_phase1(const S* __restrict__ src, const La
     }
 }
 
+// Phase 2 of an interior tile with FP32 storage, two nodes per lane: lane L of a
+// half-wave advances the nodes 2L and 2L + 1 of one tile row from LDS and stores each
+// population of the pair as one aligned 8-byte word (half as many store instructions as
+// one node per lane, 2% faster on the 4096^2 cavity; for binary16 storage the 4-byte pair
+// word gave nothing).
+template <int SRC, int TY, int NT>
+__device__ __forceinline__ void step2_phase2_pairs(float* __restrict__ dst, const LatticeConst& c,
+                                                   const float* tile, int X0, int Y0, int lane, int wave)
+{
+    typedef Tile2<TY> T;
+    typedef float F2 __attribute__((ext_vector_type(2)));
+    constexpr int nwaves = NT / 64;
+    const int L = lane & 31, sub = lane >> 5;
+    constexpr unsigned e = sizeof(float), rb = T::XE * sizeof(float);
+    const unsigned pairb = (((unsigned)X0 / kBlock) * kBlockElems + 2u * (unsigned)L) * e;
+#pragma unroll
+    for (int j = 0; j < (TY + 2 * nwaves - 1) / (2 * nwaves); ++j) {
+        const int ly = 2 * wave + sub + j * 2 * nwaves;
+        if (ly >= TY) break;
+        const char* rc = reinterpret_cast<const char*>(tile) + (unsigned)(ly + 1) * rb;
+        float v[2][14];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            // LDS column of the node is its tile column + 1 (the ring is column 0)
+            const unsigned cb = (unsigned)(2 * L + h + 1) * e;
+            const ColBytes k{cb - e, cb, cb + e};
+            float a[9], b[5];
+            double fa[9], tb[5];
+            NodeMacro m;
+            gather_interior<float, T::P>(rc - rb, rc, rc + rb, k, a, b);
+            collide<float, SRC, double>(c, a, b, fa, tb, m, node_q<SRC>(c, X0 + 2 * L + h, Y0 + ly));
+            round_node<float>(fa, tb, v[h], X0 + 2 * L + h, Y0 + ly);
+        }
+        char* out = stored_row(dst, c.rowlen, Y0 + ly) + pairb;
+#pragma unroll
+        for (int i = 0; i < 14; ++i) {
+            F2 w;
+            w.x = v[0][i];
+            w.y = v[1][i];
+            __builtin_nontemporal_store(w, reinterpret_cast<F2*>(out + i * kBlock * e));
+        }
+    }
+}
+
 // Phase 2 for thread tid: the tile's own nodes advanced from LDS and stored.
 template <typename S, int SRC, int TY, int NT, typename O>
 __device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeConst& c, const S* tile,
@@ -488,6 +532,12 @@ __device__ __forceinline__ void step2_phase2(S* __restrict__ dst, const LatticeC
     const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
     constexpr int nwaves = NT / 64;
     const int gx = X0 + lane;
+    if constexpr (sizeof(S) == 4) {
+        if (tile_interior<TY>(c, X0, Y0)) {
+            step2_phase2_pairs<SRC, TY, NT>(dst, c, tile, X0, Y0, lane, wave);
+            return;
+        }
+    }
     if (tile_interior<TY>(c, X0, Y0)) {
         // LDS column of the node is lane + 1, its row ly + 1 (the ring is row and column 0)
         const unsigned e = (unsigned)sizeof(S), cb = (unsigned)(lane + 1) * e;
