@@ -111,7 +111,7 @@ def kernel_avg_ms(torch, s, launches):
     return e0.elapsed_time(e1) / launches, spl
 
 
-def copy_ceiling(torch, clbm, nbytes=2 << 30, reps=10):
+def copy_ceiling(torch, clbm, nbytes=2 << 30, reps=40):
     """GB/s of the library's plain streaming copy (read + write) over nbytes buffers."""
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
@@ -1023,9 +1023,9 @@ def main():
         s.set_graph(gsteps)          # instantiates both graphs before anything is timed
     T0 = torch.from_numpy(W.cavity_initial_T(prob, seed=12345).astype(np.float32))
     s.init(T=T0)
-    # The reference copy runs first: besides the ceiling it reports, its 24 GB of streaming
-    # bring the shader and memory clocks out of idle, so that a short timed region is not
-    # measured on the first launches after idle.
+    # The reference copy runs first: besides the ceiling it reports (40 timed copies of
+    # 2 GiB, about 28 ms), its streaming brings the shader and memory clocks out of idle,
+    # so that a short timed region is not measured on the first launches after idle.
     copy_gbs, copy_ms = copy_ceiling(torch, clbm)
     log("bench: reference copy %.0f GB/s" % copy_gbs)
     log("bench: %dx%d %s, warmup %d, graphs of %d steps" % (args.n, args.n, args.precision, args.warmup, gsteps))
