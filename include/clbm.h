@@ -298,7 +298,9 @@ clbm_status clbm_batch_reset(clbm_batch* b);
  * max_steps steps since clbm_batch_reset, or until this call has advanced budget_steps
  * steps (budget_steps <= 0: no budget); a later call resumes. Convergence checks,
  * retirement and compaction of the tile list run on the device inside a replayed HIP
- * graph of K steps. Synchronises. steps_out[i] is the number of steps instance i has
+ * graph of K steps. With FP16 storage the residual settles at about 5e-7 to 1e-6 (the
+ * unbiased rounding into binary16 keeps moving the stored state by rounding noise), so tol
+ * must lie above that floor (2e-6, say). Synchronises. steps_out[i] is the number of steps instance i has
  * taken (for a retired instance, the step it stopped at), status_out[i] its CLBM_INST_*
  * code; host arrays of length n. */
 clbm_status clbm_batch_run(clbm_batch* b, long max_steps, double tol, int K, long budget_steps,
