@@ -479,7 +479,8 @@ class Batch:
         reset is False (then the previous run resumes). With chunk > 0 the run proceeds
         in calls of at most chunk steps and progress(steps, status) is called after each;
         max_calls > 0 stops after that many calls. Returns (steps, status) per instance;
-        status names from INST_STATUS."""
+        status names from INST_STATUS. With FP16 storage the residual floor is about 1e-6:
+        choose tol above it."""
         if reset:
             _check(lib().clbm_batch_reset(self._h), "clbm_batch_reset")
         steps = (ctypes.c_long * self.n)()
