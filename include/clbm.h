@@ -200,14 +200,15 @@ clbm_status clbm_populations(clbm_handle* h, float* d_f, float* d_g);
 clbm_status clbm_diagnostics(clbm_handle* h, clbm_diag* out);
 
 /* For callers that cannot allocate device memory or use a workspace of their own at
- * this point (code under HIP graph capture, tight serving loops): clbm_diagnostics with
+ * this point (tight serving loops, harnesses that forbid allocation): clbm_diagnostics with
  * the reduction's partial and final sums in a fixed library-owned device array (155 KB
  * per GPU, held until the process ends; resolved per device at clbm_create) instead of
  * the handle's workspace. Calls no hipMalloc or hipFree. The array holds the partials of
  * any lattice size (the reduction grid is capped at 1024 workgroups); a request beyond
  * it would return CLBM_ERR_BUFFER_TOO_SMALL. All handles on one GPU share the array, so
  * calls that overlap on one GPU race: order them on one stream. Same results, residual
- * snapshot update, synchronisation and errors as clbm_diagnostics. */
+ * snapshot update, synchronisation and errors as clbm_diagnostics; like it, the call
+ * waits for the stream, so it cannot be recorded into a stream capture. */
 clbm_status clbm_diagnostics_noalloc(clbm_handle* h, clbm_diag* out);
 
 /* Checkpoint: the state occupies clbm_state_bytes; save copies it to d_dst,
